@@ -1,0 +1,500 @@
+"""Plain float64 CPU oracle for guided linear upsampling (GLU).
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path imports, calls or
+links this module: only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` use it, to check the HIP kernels and to
+time a CPU reference.  It shares no code with the HIP path.
+
+Written from the paper (Song et al., "Guided Linear Upsampling", ACM TOG
+42(4), 2023).  Every step follows the paper's definitions in their stated
+order; NumPy arrays run each step over many pixels at once, but no step is
+blocked, fused or reordered.  All arithmetic is float64: inputs that arrive
+as float32 or float16 are upcast exactly.
+
+Notation (Sec. 3.1):
+  I      high-resolution guide, H x W x 3
+  L      low-resolution guide I_down, h x w x 3, h = ceil(H/s), w = ceil(W/s)
+  p_down (y // s, x // s), the LR cell under HR pixel p
+  Omega  the k x k LR cells centred on p_down, truncated at the LR border
+  Theta  per pixel (a, b, alpha): LR linear indices of the two endpoints and
+         the weight on a
+  E      per-pixel error ||I_p - I_hat_p|| (Euclidean over RGB, not squared)
+
+Readings of points the paper leaves open (each also listed in the design
+notes of the repository):
+  * alpha from the projection formula (Eq. 4) is clamped to [0, 1]: the
+    model is an interpolation (Eq. 1) and the fast weight (Eq. 5) is in
+    [0, 1] by construction.
+  * The candidate set of the exhaustive search holds every unordered pair
+    i < j of the window (36 for 3 x 3, Sec. 3.2) plus the degenerate pairs
+    (i, i) with alpha = 1, which make nearest-neighbour upsampling (GNU,
+    Sec. 3.2) a special case of the search.
+  * Candidates are visited in colexicographic order of (i, j) in LR linear
+    index (second index outer, first index inner, (j, j) after (i < j, j));
+    the first strict minimum wins, so exact ties go to the earliest
+    candidate in that order.  The fast search takes the anchor a as the
+    first minimum of the colour distance and b as the first minimum of the
+    error, both in ascending LR index.
+  * If a denominator is zero (only possible with eps = 0) the weight is 1.
+  * The same eps (default 1e-3, Sec. 3.1) is used in Eq. 4 and Eq. 5.
+  * Joint downsampling (Alg. 2): 8-connected components, ordered by their
+    first pixel in raster order, processed one after another; by default
+    the pixels re-searched and summed for e0 / e1 are the whole affected
+    set A = {p : Omega(p) meets Q}; ``reading="literal"`` re-searches and
+    sums over the component only.  Rollback when e1 > e0 (strict).
+    Arg-max ties go to the smallest HR linear index.
+"""
+from __future__ import annotations
+
+import math
+from collections import deque
+from dataclasses import dataclass, field
+
+import numpy as np
+
+__all__ = [
+    "EPS",
+    "TAU",
+    "N_ITER",
+    "WINDOW",
+    "lr_shape",
+    "downsample_point",
+    "downsample_box",
+    "window_cells",
+    "search_exhaustive",
+    "search_fast",
+    "search",
+    "apply",
+    "apply_backward",
+    "reconstruct",
+    "ccl8",
+    "joint_downsample",
+    "JointResult",
+]
+
+# Parameters fixed by the paper: eps of Eq. 4 (Sec. 3.1); window S = 3,
+# tau = 30/255 and N = 3 iterations (Sec. 5.2).
+EPS = 1e-3
+WINDOW = 3
+TAU = 30.0 / 255.0
+N_ITER = 3
+
+
+def lr_shape(H: int, W: int, s: int) -> tuple[int, int]:
+    """LR size for ratio s: every HR pixel has a cell, so ceil(H/s) x ceil(W/s)."""
+    return (-(-H // s), -(-W // s))
+
+
+# --------------------------------------------------------------------------
+# Downsampling (inputs of the search)
+# --------------------------------------------------------------------------
+def downsample_point(I: np.ndarray, s: int) -> np.ndarray:
+    """Regular-grid downsampling (Sec. 3.1, Alg. 2 initialisation).
+
+    Each LR pixel is a copy of exactly one HR pixel (Sec. 3.3): the pixel at
+    offset floor(s/2) inside its s x s block, clamped into the image.
+    Returns an array of I's dtype (a copy of stored values, no rounding).
+    """
+    I = np.asarray(I)
+    H, W = I.shape[:2]
+    h, w = lr_shape(H, W, s)
+    ys = np.minimum(np.arange(h) * s + s // 2, H - 1)
+    xs = np.minimum(np.arange(w) * s + s // 2, W - 1)
+    return np.ascontiguousarray(I[ys][:, xs])
+
+
+def downsample_box(I: np.ndarray, s: int) -> np.ndarray:
+    """Box downsampling: mean of the in-image pixels of each s x s block (float64)."""
+    I = np.asarray(I, dtype=np.float64)
+    H, W, C = I.shape
+    h, w = lr_shape(H, W, s)
+    out = np.zeros((h, w, C), dtype=np.float64)
+    for qy in range(h):
+        for qx in range(w):
+            blk = I[qy * s : min(H, qy * s + s), qx * s : min(W, qx * s + s)]
+            out[qy, qx] = blk.reshape(-1, C).mean(axis=0)
+    return out
+
+
+# --------------------------------------------------------------------------
+# Windows
+# --------------------------------------------------------------------------
+def window_cells(qy: int, qx: int, h: int, w: int, k: int) -> list[int]:
+    """LR linear indices of Omega around cell (qy, qx), ascending, border-truncated."""
+    r = k // 2
+    out = []
+    for dy in range(-r, r + 1):
+        for dx in range(-r, r + 1):
+            y, x = qy + dy, qx + dx
+            if 0 <= y < h and 0 <= x < w:
+                out.append(y * w + x)
+    return out
+
+
+def _pixel_coords(H: int, W: int, pixels):
+    if pixels is None:
+        ys, xs = np.divmod(np.arange(H * W, dtype=np.int64), W)
+    else:
+        pixels = np.asarray(pixels, dtype=np.int64).ravel()
+        ys, xs = np.divmod(pixels, W)
+    return ys, xs
+
+
+def _candidates(ys, xs, s, h, w, k):
+    """Per window offset (ascending): validity mask and LR linear index per pixel."""
+    r = k // 2
+    qy = ys // s
+    qx = xs // s
+    out = []
+    for dy in range(-r, r + 1):
+        for dx in range(-r, r + 1):
+            cy = qy + dy
+            cx = qx + dx
+            valid = (cy >= 0) & (cy < h) & (cx >= 0) & (cx < w)
+            lin = np.where(valid, cy * w + cx, 0)
+            out.append((valid, lin))
+    return out
+
+
+@dataclass
+class SearchResult:
+    a: np.ndarray  # LR linear index of endpoint a (weight alpha)
+    b: np.ndarray  # LR linear index of endpoint b (weight 1 - alpha)
+    alpha: np.ndarray
+    err: np.ndarray  # ||alpha L_a + (1 - alpha) L_b - I_p||
+    pixels: np.ndarray | None = None  # flat HR indices searched (None: all)
+
+
+def search_exhaustive(I, L, s, k=WINDOW, eps=EPS, pixels=None, degenerate=True) -> SearchResult:
+    """Per-pixel pair search over all pairs of the window (Eq. 3 with Eq. 4).
+
+    For every candidate pair (i, j), i <= j, of Omega(p):
+        alpha = 1                                   if i == j
+        alpha = clamp(((I_p - L_j) . (L_i - L_j)) / (||L_i - L_j||^2 + eps), 0, 1)
+                                                    otherwise (1 if the denominator is 0)
+        err   = ||alpha L_i + (1 - alpha) L_j - I_p||
+    and keep the pair with the least err (first in colexicographic order on
+    exact ties).  ``pixels`` restricts the search to flat HR indices.
+    ``degenerate=False`` drops the (i, i) candidates except in a window with
+    a single cell (the paper's literal 36 pairs for 3 x 3).
+    """
+    I = np.asarray(I, dtype=np.float64)
+    L = np.asarray(L, dtype=np.float64)
+    H, W = I.shape[:2]
+    h, w = L.shape[:2]
+    if (h, w) != lr_shape(H, W, s):
+        raise ValueError("I_low must be ceil(H/s) x ceil(W/s)")
+    ys, xs = _pixel_coords(H, W, pixels)
+    Ip = I[ys, xs]  # (n, 3)
+    Lf = L.reshape(-1, L.shape[2])
+    cand = _candidates(ys, xs, s, h, w, k)
+    n = Ip.shape[0]
+    best = np.full(n, np.inf)
+    a = np.full(n, -1, dtype=np.int64)
+    b = np.full(n, -1, dtype=np.int64)
+    alpha = np.full(n, np.nan)
+    cols = [Lf[lin] for (_, lin) in cand]
+    K = len(cand)
+    for j in range(K):  # colexicographic: second index outer
+        vj, linj = cand[j]
+        Lj = cols[j]
+        for i in range(j + 1):
+            vi, lini = cand[i]
+            Li = cols[i]
+            if i == j:
+                if not degenerate:
+                    continue
+                al = np.ones(n)
+            else:
+                e = Li - Lj
+                den = np.einsum("nc,nc->n", e, e) + eps
+                g = np.einsum("nc,nc->n", Ip - Lj, e)
+                with np.errstate(divide="ignore", invalid="ignore"):
+                    al = np.where(den > 0, np.clip(g / np.where(den > 0, den, 1.0), 0.0, 1.0), 1.0)
+            rec = al[:, None] * Li + (1.0 - al)[:, None] * Lj
+            err = np.sqrt(np.einsum("nc,nc->n", rec - Ip, rec - Ip))
+            upd = vi & vj & (err < best)
+            best = np.where(upd, err, best)
+            a = np.where(upd, lini, a)
+            b = np.where(upd, linj, b)
+            alpha = np.where(upd, al, alpha)
+    if not degenerate:
+        # A window with a single cell has no proper pair: use its only cell.
+        lone = a < 0
+        if lone.any():
+            for j in range(K):
+                vj, linj = cand[j]
+                take = lone & vj
+                d = Ip - cols[j]
+                err = np.sqrt(np.einsum("nc,nc->n", d, d))
+                a = np.where(take, linj, a)
+                b = np.where(take, linj, b)
+                alpha = np.where(take, 1.0, alpha)
+                best = np.where(take, err, best)
+                lone = lone & ~vj
+    return SearchResult(a=a, b=b, alpha=alpha, err=best, pixels=None if pixels is None else np.asarray(pixels))
+
+
+def search_fast(I, L, s, k=WINDOW, eps=EPS, pixels=None) -> SearchResult:
+    """Efficient search of Algorithm 1 with the weight of Eq. 5.
+
+    a = the window cell of most similar colour to I_p (least Euclidean
+    distance; first in ascending LR index on ties).  Then, with a fixed, for
+    each b of the window (b = a allowed, weight 1):
+        w_b   = ||I_p - L_b|| / (||I_p - L_a|| + ||I_p - L_b|| + eps)
+        err_b = ||w_b L_a + (1 - w_b) L_b - I_p||
+    and keep the first b of least err.
+    """
+    I = np.asarray(I, dtype=np.float64)
+    L = np.asarray(L, dtype=np.float64)
+    H, W = I.shape[:2]
+    h, w = L.shape[:2]
+    if (h, w) != lr_shape(H, W, s):
+        raise ValueError("I_low must be ceil(H/s) x ceil(W/s)")
+    ys, xs = _pixel_coords(H, W, pixels)
+    Ip = I[ys, xs]
+    Lf = L.reshape(-1, L.shape[2])
+    cand = _candidates(ys, xs, s, h, w, k)
+    n = Ip.shape[0]
+    cols = [Lf[lin] for (_, lin) in cand]
+    dist = []
+    for (v, _), Lc in zip(cand, cols):
+        d = Ip - Lc
+        dist.append(np.where(v, np.sqrt(np.einsum("nc,nc->n", d, d)), np.inf))
+    # anchor
+    da = np.full(n, np.inf)
+    ia = np.full(n, -1, dtype=np.int64)
+    for idx, dd in enumerate(dist):
+        upd = dd < da
+        da = np.where(upd, dd, da)
+        ia = np.where(upd, idx, ia)
+    rows = np.arange(n)
+    lin_all = np.stack([lin for (_, lin) in cand], axis=1)
+    col_all = np.stack(cols, axis=1)  # (n, K, 3)
+    a = lin_all[rows, ia]
+    La = col_all[rows, ia]
+    best = np.full(n, np.inf)
+    b = np.full(n, -1, dtype=np.int64)
+    omega = np.full(n, np.nan)
+    for idx, ((v, lin), Lb) in enumerate(zip(cand, cols)):
+        same = ia == idx
+        den = da + dist[idx] + eps
+        with np.errstate(divide="ignore", invalid="ignore"):
+            om = np.where(den > 0, dist[idx] / np.where(den > 0, den, 1.0), 1.0)
+        om = np.where(same, 1.0, om)
+        rec = om[:, None] * La + (1.0 - om)[:, None] * Lb
+        err = np.sqrt(np.einsum("nc,nc->n", rec - Ip, rec - Ip))
+        upd = v & (err < best)
+        best = np.where(upd, err, best)
+        b = np.where(upd, lin, b)
+        omega = np.where(upd, om, omega)
+    return SearchResult(a=a, b=b, alpha=omega, err=best, pixels=None if pixels is None else np.asarray(pixels))
+
+
+def search(I, L, s, k=WINDOW, eps=EPS, mode="exhaustive", pixels=None) -> SearchResult:
+    if mode == "exhaustive":
+        return search_exhaustive(I, L, s, k, eps, pixels)
+    if mode == "fast":
+        return search_fast(I, L, s, k, eps, pixels)
+    raise ValueError("mode must be 'exhaustive' or 'fast'")
+
+
+# --------------------------------------------------------------------------
+# Apply (Eq. 1) and its backward
+# --------------------------------------------------------------------------
+def apply(a, b, alpha, T_low) -> np.ndarray:
+    """Eq. 1: T_hat_p = alpha T_low[a] + (1 - alpha) T_low[b], per channel.
+
+    ``a``, ``b``, ``alpha`` have the HR shape (H, W) (or any shape); returns
+    that shape plus the channel axis of ``T_low`` (h, w, C).
+    """
+    T = np.asarray(T_low, dtype=np.float64)
+    Tf = T.reshape(-1, T.shape[-1])
+    al = np.asarray(alpha, dtype=np.float64)[..., None]
+    return al * Tf[np.asarray(a)] + (1.0 - al) * Tf[np.asarray(b)]
+
+
+def reconstruct(a, b, alpha, L) -> np.ndarray:
+    """I_hat: Eq. 1 applied to the LR guide itself (self-upsampling, Sec. 3.3)."""
+    return apply(a, b, alpha, L)
+
+
+def apply_backward(a, b, alpha, T_low, G):
+    """Gradients of Eq. 1 with Theta held fixed.
+
+    dL/dalpha_p  = sum_c G_p,c (T_low[a_p],c - T_low[b_p],c)
+    dL/dT_low_q  = sum_{p: a_p = q} alpha_p G_p + sum_{p: b_p = q} (1 - alpha_p) G_p
+    """
+    T = np.asarray(T_low, dtype=np.float64)
+    C = T.shape[-1]
+    Tf = T.reshape(-1, C)
+    a = np.asarray(a).ravel()
+    b = np.asarray(b).ravel()
+    al = np.asarray(alpha, dtype=np.float64).ravel()
+    Gf = np.asarray(G, dtype=np.float64).reshape(-1, C)
+    d_alpha = np.einsum("nc,nc->n", Gf, Tf[a] - Tf[b])
+    dT = np.zeros_like(Tf)
+    np.add.at(dT, a, al[:, None] * Gf)
+    np.add.at(dT, b, (1.0 - al)[:, None] * Gf)
+    return d_alpha.reshape(np.shape(alpha)), dT.reshape(T.shape)
+
+
+# --------------------------------------------------------------------------
+# Joint optimisation of down- and upsampling (Sec. 3.3, Alg. 2)
+# --------------------------------------------------------------------------
+def ccl8(mask: np.ndarray):
+    """8-connected components of a boolean mask.
+
+    Returns (labels, M): labels is int32 with 0 for background and 1..M for
+    components numbered in the raster order of their first pixel.
+    """
+    mask = np.asarray(mask, dtype=bool)
+    H, W = mask.shape
+    labels = np.zeros((H, W), dtype=np.int32)
+    M = 0
+    for start in np.flatnonzero(mask):
+        y0, x0 = divmod(int(start), W)
+        if labels[y0, x0]:
+            continue
+        M += 1
+        labels[y0, x0] = M
+        queue = deque([(y0, x0)])
+        while queue:
+            y, x = queue.popleft()
+            for dy in (-1, 0, 1):
+                for dx in (-1, 0, 1):
+                    ny, nx = y + dy, x + dx
+                    if 0 <= ny < H and 0 <= nx < W and mask[ny, nx] and not labels[ny, nx]:
+                        labels[ny, nx] = M
+                        queue.append((ny, nx))
+    return labels, M
+
+
+@dataclass
+class Decision:
+    round: int
+    first_pixel: int
+    accepted: bool
+    e0: float
+    e1: float
+    q_pstar: list  # [(q, p_star), ...] in ascending q
+
+
+@dataclass
+class JointResult:
+    L: np.ndarray  # optimised LR guide (h, w, 3), float64 copies of I pixels
+    a: np.ndarray
+    b: np.ndarray
+    alpha: np.ndarray
+    err: np.ndarray
+    rounds_run: int = 0
+    n_large: list = field(default_factory=list)
+    n_components: list = field(default_factory=list)
+    n_accepted: list = field(default_factory=list)
+    err_sum_initial: float = 0.0
+    err_sum_final: float = 0.0
+    log: list = field(default_factory=list)
+
+
+def _affected_pixels(Q, h, w, H, W, s, k):
+    """A = {p : Omega(p) contains some q of Q}: pixels whose cell is within r of Q."""
+    r = k // 2
+    cells = np.zeros((h, w), dtype=bool)
+    for q in Q:
+        qy, qx = divmod(int(q), w)
+        cells[max(0, qy - r) : qy + r + 1, max(0, qx - r) : qx + r + 1] = True
+    ys, xs = np.divmod(np.arange(H * W, dtype=np.int64), W)
+    sel = cells[ys // s, xs // s]
+    return np.flatnonzero(sel)
+
+
+def joint_downsample(
+    I,
+    L0,
+    s,
+    k=WINDOW,
+    eps=EPS,
+    mode="exhaustive",
+    tau=TAU,
+    max_iter=N_ITER,
+    reading="affected",
+    decide=None,
+) -> JointResult:
+    """Algorithm 2: alternate the pair search with trial replacements of I_down.
+
+    I_down starts at ``L0`` (regular-grid downsampling by default, Alg. 2)
+    and Theta, E at the search on it.  Each of up to ``max_iter`` rounds:
+      1. large-error set {p : E_p > tau}; stop if empty;
+      2. its 8-connected components C_1..C_M (raster order of first pixel);
+      3. for each component in turn: back up I_down, Theta, E; e0 = sum of
+         E over the pixels re-evaluated; for every LR cell q whose block
+         meets C_i set I_down[q] = I[p*], p* the pixel of [q_up] & C_i with
+         the largest E; re-search; e1 = the same sum; roll back if e1 > e0.
+    ``decide`` (optional) is called as decide(kind, payload, default) at each
+    decision so a test can replay another implementation's near-tie
+    decisions; it must return the decision to take.
+    """
+    I = np.asarray(I, dtype=np.float64)
+    H, W = I.shape[:2]
+    L = np.array(L0, dtype=np.float64, copy=True)
+    h, w = L.shape[:2]
+    Lf = L.reshape(h * w, -1)  # view
+    If = I.reshape(H * W, -1)
+    r0 = search(I, L, s, k, eps, mode)
+    a, b, alpha, E = r0.a.copy(), r0.b.copy(), r0.alpha.copy(), r0.err.copy()
+    res = JointResult(L=L, a=a, b=b, alpha=alpha, err=E, err_sum_initial=float(E.sum()))
+    ys_all, xs_all = np.divmod(np.arange(H * W, dtype=np.int64), W)
+    cell_of = (ys_all // s) * w + (xs_all // s)
+    for n in range(1, max_iter + 1):
+        large = E > tau
+        if decide is not None:
+            large = decide("membership", E, large)
+        if not large.any():
+            break
+        labels, M = ccl8(large.reshape(H, W))
+        res.rounds_run = n
+        res.n_large.append(int(large.sum()))
+        res.n_components.append(M)
+        acc_count = 0
+        lab_flat = labels.ravel()
+        order = np.flatnonzero(lab_flat)
+        comp_pixels: list[list[int]] = [[] for _ in range(M + 1)]
+        for p in order:  # raster order inside each component
+            comp_pixels[lab_flat[p]].append(int(p))
+        for ci in range(1, M + 1):
+            C = np.asarray(comp_pixels[ci], dtype=np.int64)
+            Q = np.unique(cell_of[C])
+            if reading == "affected":
+                A = _affected_pixels(Q, h, w, H, W, s, k)
+            elif reading == "literal":
+                A = C
+            else:
+                raise ValueError("reading must be 'affected' or 'literal'")
+            bak_L = Lf[Q].copy()
+            bak = (a[A].copy(), b[A].copy(), alpha[A].copy(), E[A].copy())
+            e0 = float(E[A].sum())
+            q_pstar = []
+            for q in Q:
+                members = C[cell_of[C] == q]  # ascending HR index
+                Em = E[members]
+                pstar = int(members[int(np.argmax(Em))])  # first maximum
+                if decide is not None:
+                    pstar = decide("argmax", (int(q), members, Em), pstar)
+                q_pstar.append((int(q), pstar))
+            for q, pstar in q_pstar:
+                Lf[q] = If[pstar]
+            rs = search(I, L, s, k, eps, mode, pixels=A)
+            a[A], b[A], alpha[A], E[A] = rs.a, rs.b, rs.alpha, rs.err
+            e1 = float(E[A].sum())
+            accept = not (e1 > e0)
+            if decide is not None:
+                accept = decide("accept", (e0, e1, A.size), accept)
+            if not accept:
+                Lf[Q] = bak_L
+                a[A], b[A], alpha[A], E[A] = bak
+            else:
+                acc_count += 1
+            res.log.append(Decision(n, int(C[0]), accept, e0, e1, q_pstar))
+        res.n_accepted.append(acc_count)
+    res.err_sum_final = float(E.sum())
+    return res
