@@ -70,6 +70,9 @@ __all__ = [
     "ccl8",
     "joint_downsample",
     "JointResult",
+    "eval_pairs_exhaustive",
+    "eval_pairs_fast",
+    "search_fast_given_anchor",
 ]
 
 # Parameters fixed by the paper: eps of Eq. 4 (Sec. 3.1); window S = 3,
@@ -498,3 +501,78 @@ def joint_downsample(
         res.n_accepted.append(acc_count)
     res.err_sum_final = float(E.sum())
     return res
+
+
+# --------------------------------------------------------------------------
+# Evaluation of given pairs (for judging another implementation's choice)
+# --------------------------------------------------------------------------
+def eval_pairs_exhaustive(I, L, pixels, a, b, eps=EPS):
+    """Eq. 4 weight (clamped, weight on a; 1 when a == b or a zero
+    denominator) and the error of the given pairs at the given pixels."""
+    I = np.asarray(I, dtype=np.float64)
+    L = np.asarray(L, dtype=np.float64)
+    W = I.shape[1]
+    ys, xs = np.divmod(np.asarray(pixels, dtype=np.int64).ravel(), W)
+    Ip = I[ys, xs]
+    Lf = L.reshape(-1, L.shape[2])
+    La, Lb = Lf[np.asarray(a)], Lf[np.asarray(b)]
+    e = La - Lb
+    den = np.einsum("nc,nc->n", e, e) + eps
+    g = np.einsum("nc,nc->n", Ip - Lb, e)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        al = np.where(den > 0, np.clip(g / np.where(den > 0, den, 1.0), 0.0, 1.0), 1.0)
+    al = np.where(np.asarray(a) == np.asarray(b), 1.0, al)
+    rec = al[:, None] * La + (1 - al)[:, None] * Lb
+    return al, np.sqrt(np.einsum("nc,nc->n", rec - Ip, rec - Ip))
+
+
+def eval_pairs_fast(I, L, pixels, a, b, eps=EPS):
+    """Eq. 5 weight on the anchor a (1 when b == a) and the error of (a, b)."""
+    I = np.asarray(I, dtype=np.float64)
+    L = np.asarray(L, dtype=np.float64)
+    W = I.shape[1]
+    ys, xs = np.divmod(np.asarray(pixels, dtype=np.int64).ravel(), W)
+    Ip = I[ys, xs]
+    Lf = L.reshape(-1, L.shape[2])
+    La, Lb = Lf[np.asarray(a)], Lf[np.asarray(b)]
+    da = np.linalg.norm(Ip - La, axis=1)
+    db = np.linalg.norm(Ip - Lb, axis=1)
+    den = da + db + eps
+    with np.errstate(divide="ignore", invalid="ignore"):
+        om = np.where(den > 0, db / np.where(den > 0, den, 1.0), 1.0)
+    om = np.where(np.asarray(a) == np.asarray(b), 1.0, om)
+    rec = om[:, None] * La + (1 - om)[:, None] * Lb
+    return om, np.sqrt(np.einsum("nc,nc->n", rec - Ip, rec - Ip))
+
+
+def search_fast_given_anchor(I, L, s, k, eps, pixels, anchor):
+    """Second step of Algorithm 1 with the anchor a given per pixel."""
+    I = np.asarray(I, dtype=np.float64)
+    L = np.asarray(L, dtype=np.float64)
+    H, W = I.shape[:2]
+    h, w = L.shape[:2]
+    ys, xs = _pixel_coords(H, W, pixels)
+    Ip = I[ys, xs]
+    Lf = L.reshape(-1, L.shape[2])
+    cand = _candidates(ys, xs, s, h, w, k)
+    anchor = np.asarray(anchor, dtype=np.int64).ravel()
+    La = Lf[anchor]
+    da = np.linalg.norm(Ip - La, axis=1)
+    n = Ip.shape[0]
+    best = np.full(n, np.inf)
+    b = np.full(n, -1, dtype=np.int64)
+    omega = np.full(n, np.nan)
+    for v, lin in cand:
+        Lb = Lf[lin]
+        db = np.linalg.norm(Ip - Lb, axis=1)
+        den = da + db + eps
+        with np.errstate(divide="ignore", invalid="ignore"):
+            om = np.where(den > 0, db / np.where(den > 0, den, 1.0), 1.0)
+        om = np.where(lin == anchor, 1.0, om)
+        rec = om[:, None] * La + (1.0 - om)[:, None] * Lb
+        err = np.sqrt(np.einsum("nc,nc->n", rec - Ip, rec - Ip))
+        upd = v & (err < best)
+        best = np.where(upd, err, best)
+        b = np.where(upd, lin, b)
+        omega = np.where(upd, om, omega)
+    return SearchResult(a=anchor, b=b, alpha=omega, err=best, pixels=np.asarray(pixels))

@@ -1,0 +1,23 @@
+"""Guided linear upsampling (Song et al., ACM TOG 2023) on AMD MI355X.
+
+The hot path (pair search, apply, its backward, joint downsampling and
+batched execution) runs in HIP kernels for gfx950 behind the C ABI of
+include/glu.h; this package is the thin torch binding over it.
+"""
+from .glu import (  # noqa: F401
+    EPS,
+    N_ITER,
+    TAU,
+    GluApply,
+    Theta,
+    apply,
+    apply_backward,
+    downsample,
+    empty_theta,
+    glu_apply_autograd,
+    lr_shape,
+    search,
+    search_apply,
+    theta_expand,
+)
+from ._lib import GluError  # noqa: F401

@@ -1,0 +1,181 @@
+"""ctypes view of the libglu C ABI (include/glu.h).
+
+Loading fails loudly: there is no fallback implementation.  The library is
+built in place by ``paper_2307_09582_amd.build_lib``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libglu.so")
+
+GLU_OK = 0
+STATUS_NAMES = {
+    0: "GLU_OK",
+    1: "GLU_ERR_NULL",
+    2: "GLU_ERR_SHAPE",
+    3: "GLU_ERR_DTYPE",
+    4: "GLU_ERR_PARAM",
+    5: "GLU_ERR_ALIGN",
+    6: "GLU_ERR_NOMEM",
+    7: "GLU_ERR_HIP",
+    8: "GLU_ERR_UNSUPPORTED",
+    9: "GLU_ERR_WORKSPACE",
+}
+GLU_F32, GLU_F16 = 0, 1
+GLU_SEARCH_EXHAUSTIVE, GLU_SEARCH_FAST = 0, 1
+GLU_DOWN_POINT, GLU_DOWN_BOX = 0, 1
+
+
+class GluError(RuntimeError):
+    def __init__(self, status: int, detail: str):
+        self.status = status
+        self.name = STATUS_NAMES.get(status, "GLU_ERR_%d" % status)
+        super().__init__("%s (%s)" % (self.name, detail))
+
+
+class glu_image(C.Structure):
+    _fields_ = [
+        ("data", C.c_void_p),
+        ("height", C.c_int32),
+        ("width", C.c_int32),
+        ("channels", C.c_int32),
+        ("row_stride", C.c_int64),
+        ("dtype", C.c_int32),
+    ]
+
+
+class glu_theta(C.Structure):
+    _fields_ = [
+        ("code", C.c_void_p),
+        ("alpha", C.c_void_p),
+        ("height", C.c_int32),
+        ("width", C.c_int32),
+        ("row_stride", C.c_int64),
+    ]
+
+
+class glu_params(C.Structure):
+    _fields_ = [
+        ("s", C.c_int32),
+        ("k", C.c_int32),
+        ("eps", C.c_float),
+        ("mode", C.c_int32),
+        ("flags", C.c_uint32),
+    ]
+
+
+class glu_jd_stats(C.Structure):
+    _fields_ = [
+        ("rounds_run", C.c_int32),
+        ("n_large", C.c_int32 * 64),
+        ("n_components", C.c_int32 * 64),
+        ("n_accepted", C.c_int32 * 64),
+        ("n_waves", C.c_int32 * 64),
+        ("err_sum_initial", C.c_double),
+        ("err_sum_final", C.c_double),
+    ]
+
+
+class glu_jd_log(C.Structure):
+    _fields_ = [
+        ("capacity", C.c_int32),
+        ("count", C.c_int32),
+        ("round", C.POINTER(C.c_int32)),
+        ("first_pixel", C.POINTER(C.c_int32)),
+        ("accepted", C.POINTER(C.c_uint8)),
+        ("e0", C.POINTER(C.c_double)),
+        ("e1", C.POINTER(C.c_double)),
+        ("n_q", C.POINTER(C.c_int32)),
+        ("q_capacity", C.c_int64),
+        ("q_and_pstar", C.POINTER(C.c_int64)),
+        ("truncated", C.c_int32),
+    ]
+
+
+class glu_batch_item(C.Structure):
+    _fields_ = [
+        ("I", glu_image),
+        ("I_low", glu_image),
+        ("T_low", glu_image),
+        ("T_hat", glu_image),
+        ("theta", glu_theta),
+        ("s", C.c_int32),
+        ("k", C.c_int32),
+    ]
+
+
+P = C.POINTER
+_SIGS = {
+    "glu_search": (C.c_int, [P(glu_image), P(glu_image), P(glu_params), P(glu_theta), C.c_void_p, C.c_void_p]),
+    "glu_apply": (C.c_int, [P(glu_theta), P(glu_image), P(glu_params), P(glu_image), C.c_void_p]),
+    "glu_search_apply": (
+        C.c_int,
+        [P(glu_image), P(glu_image), P(glu_image), P(glu_params), P(glu_theta), C.c_void_p, P(glu_image), C.c_void_p],
+    ),
+    "glu_apply_backward": (
+        C.c_int,
+        [P(glu_theta), P(glu_image), P(glu_params), P(glu_image), P(glu_image), C.c_void_p, C.c_void_p],
+    ),
+    "glu_downsample": (C.c_int, [P(glu_image), P(glu_image), C.c_int32, C.c_int32, C.c_void_p]),
+    "glu_theta_expand": (C.c_int, [P(glu_theta), P(glu_params), C.c_void_p, C.c_void_p, C.c_void_p]),
+    "glu_joint_downsample_workspace": (C.c_size_t, [C.c_int32, C.c_int32, P(glu_params)]),
+    "glu_joint_downsample": (
+        C.c_int,
+        [
+            P(glu_image),
+            P(glu_image),
+            P(glu_params),
+            C.c_float,
+            C.c_int32,
+            P(glu_theta),
+            C.c_void_p,
+            C.c_void_p,
+            C.c_size_t,
+            P(glu_jd_stats),
+            P(glu_jd_log),
+            C.c_void_p,
+        ],
+    ),
+    "glu_batch_plan_create": (C.c_int, [P(glu_batch_item), C.c_int32, P(glu_params), P(C.c_void_p)]),
+    "glu_batch_plan_launch": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "glu_batch_plan_destroy": (None, [C.c_void_p]),
+    "glu_batch_plan_info": (C.c_int, [C.c_void_p, P(C.c_int64), P(C.c_int32)]),
+    "glu_autotune": (C.c_int, [P(glu_batch_item), P(glu_params), P(C.c_int32), C.c_void_p]),
+    "glu_autotune_save": (C.c_int, [C.c_char_p]),
+    "glu_autotune_load": (C.c_int, [C.c_char_p]),
+    "glu_status_string": (C.c_char_p, [C.c_int]),
+    "glu_last_error": (C.c_char_p, []),
+    "glu_version": (C.c_char_p, []),
+}
+
+_lib = None
+
+
+def load(path: str | None = None):
+    """Loads libglu.so once; raises if it is missing or lacks a symbol."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise RuntimeError(
+            "libglu.so not found at %s: build it with `python -m paper_2307_09582_amd.build_lib` "
+            "(there is no fallback implementation)" % p
+        )
+    lib = C.CDLL(p)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(lib, name)  # AttributeError names a missing symbol
+        fn.restype = res
+        fn.argtypes = args
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def check(status: int):
+    if status != GLU_OK:
+        lib = load()
+        raise GluError(status, lib.glu_last_error().decode(errors="replace"))

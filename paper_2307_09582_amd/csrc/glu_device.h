@@ -1,0 +1,594 @@
+// Device code of the GLU hot path: per-pixel pair search (Sec. 3.1 Eq. 3-4,
+// Sec. 3.2 Algorithm 1 / Eq. 5) and the apply step (Sec. 3.1 Eq. 1), written
+// for gfx950 (wave64, LDS-staged LR windows, VALU fp32 arithmetic).
+//
+// Work decomposition.  A workgroup of 256 threads owns a tile of
+// tqy x tqx LR cells ("centres") and every HR pixel whose LR cell is one of
+// them (tqy*s rows by tqx*s columns).  It stages the LR cells of the tile
+// plus an r-cell halo in LDS once; in exhaustive mode it also precomputes,
+// per centre and per unordered window pair (i, j), the constants
+// e = L_i - L_j and 1 / (|e|^2 + eps) shared by the s*s pixels of that centre.
+// Each thread then takes strips of P consecutive pixels of one row, all with
+// the same centre (P divides s), loads them with vector loads and runs the
+// candidate loop with the pair constants read from LDS.
+#pragma once
+
+#include "glu_internal.h"
+
+namespace glu {
+
+// ---------------------------------------------------------------------------
+// element conversion
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ float to_f(T v);
+template <>
+__device__ __forceinline__ float to_f<float>(float v) { return v; }
+template <>
+__device__ __forceinline__ float to_f<__half>(__half v) { return __half2float(v); }
+
+template <typename T>
+__device__ __forceinline__ T from_f(float v);
+template <>
+__device__ __forceinline__ float from_f<float>(float v) { return v; }
+template <>
+__device__ __forceinline__ __half from_f<__half>(float v) { return __float2half_rn(v); }
+
+__device__ __forceinline__ float clamp01(float x) { return __builtin_amdgcn_fmed3f(x, 0.0f, 1.0f); }
+
+// ---------------------------------------------------------------------------
+// HR strip loads and stores (P consecutive pixels of one row)
+// ---------------------------------------------------------------------------
+// Loads the 3 guide channels of pixels x .. x+P-1 of `row`.  `vec` says the
+// row base allows P-pixel vector loads (P = 4: 16 bytes for float, 8 bytes for
+// half, x a multiple of 4); `full` that all P pixels lie inside the image.
+template <typename T, int P>
+__device__ __forceinline__ void load_strip3(const T* __restrict__ row, int x, int W, bool vec,
+                                            bool full, float (&ip)[P][3]) {
+  const T* p = row + (int64_t)x * 3;
+  if constexpr (P == 4 && sizeof(T) == 4) {
+    if (vec && full) {
+      const float4* q = reinterpret_cast<const float4*>(p);
+      float4 a = q[0], b = q[1], c = q[2];
+      ip[0][0] = a.x; ip[0][1] = a.y; ip[0][2] = a.z;
+      ip[1][0] = a.w; ip[1][1] = b.x; ip[1][2] = b.y;
+      ip[2][0] = b.z; ip[2][1] = b.w; ip[2][2] = c.x;
+      ip[3][0] = c.y; ip[3][1] = c.z; ip[3][2] = c.w;
+      return;
+    }
+  }
+  if constexpr (P == 4 && sizeof(T) == 2) {
+    if (vec && full) {
+      const uint2* q = reinterpret_cast<const uint2*>(p);
+      uint2 u0 = q[0], u1 = q[1], u2 = q[2];
+      const __half* h0 = reinterpret_cast<const __half*>(&u0);
+      const __half* h1 = reinterpret_cast<const __half*>(&u1);
+      const __half* h2 = reinterpret_cast<const __half*>(&u2);
+      float f[12];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        f[i] = __half2float(h0[i]);
+        f[4 + i] = __half2float(h1[i]);
+        f[8 + i] = __half2float(h2[i]);
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        ip[i][0] = f[3 * i];
+        ip[i][1] = f[3 * i + 1];
+        ip[i][2] = f[3 * i + 2];
+      }
+      return;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < P; ++i) {
+    const bool ok = full || (x + i < W);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) ip[i][c] = ok ? to_f<T>(p[3 * i + c]) : 0.0f;
+  }
+}
+
+template <int P>
+__device__ __forceinline__ void store_theta(uint16_t* __restrict__ code_row, float* __restrict__ alpha_row,
+                                            float* __restrict__ err_row, int x, int W, bool vec, bool full,
+                                            const int (&code)[P], const float (&al)[P], const float (&e)[P]) {
+  if constexpr (P == 4) {
+    if (vec && full) {
+      if (code_row) {
+        uint2 c;
+        c.x = (uint32_t)code[0] | ((uint32_t)code[1] << 16);
+        c.y = (uint32_t)code[2] | ((uint32_t)code[3] << 16);
+        *reinterpret_cast<uint2*>(code_row + x) = c;
+        *reinterpret_cast<float4*>(alpha_row + x) = make_float4(al[0], al[1], al[2], al[3]);
+      }
+      if (err_row) *reinterpret_cast<float4*>(err_row + x) = make_float4(e[0], e[1], e[2], e[3]);
+      return;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < P; ++i) {
+    if (full || x + i < W) {
+      if (code_row) {
+        code_row[x + i] = (uint16_t)code[i];
+        alpha_row[x + i] = al[i];
+      }
+      if (err_row) err_row[x + i] = e[i];
+    }
+  }
+}
+
+// Stores C channels (C <= 4) of pixels x .. x+P-1.
+template <typename T, int P>
+__device__ __forceinline__ void store_out(T* __restrict__ row, int x, int W, int C, bool vec, bool full,
+                                          const float (&o)[P][4]) {
+  T* p = row + (int64_t)x * C;
+  if constexpr (P == 4 && sizeof(T) == 4) {
+    if (vec && full && C == 3) {
+      float4* q = reinterpret_cast<float4*>(p);
+      q[0] = make_float4(o[0][0], o[0][1], o[0][2], o[1][0]);
+      q[1] = make_float4(o[1][1], o[1][2], o[2][0], o[2][1]);
+      q[2] = make_float4(o[2][2], o[3][0], o[3][1], o[3][2]);
+      return;
+    }
+    if (vec && full && C == 1) {
+      *reinterpret_cast<float4*>(p) = make_float4(o[0][0], o[1][0], o[2][0], o[3][0]);
+      return;
+    }
+  }
+  if constexpr (P == 4 && sizeof(T) == 2) {
+    if (vec && full && C == 3) {
+      __half h[12];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) h[3 * i + c] = __float2half_rn(o[i][c]);
+      uint2* q = reinterpret_cast<uint2*>(p);
+      const uint2* hv = reinterpret_cast<const uint2*>(h);
+      q[0] = hv[0];
+      q[1] = hv[1];
+      q[2] = hv[2];
+      return;
+    }
+    if (vec && full && C == 1) {
+      __half h[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) h[i] = __float2half_rn(o[i][0]);
+      *reinterpret_cast<uint2*>(p) = *reinterpret_cast<const uint2*>(h);
+      return;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < P; ++i) {
+    if (full || x + i < W) {
+      for (int c = 0; c < C; ++c) p[i * C + c] = from_f<T>(o[i][c]);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Pair constants and weights
+// ---------------------------------------------------------------------------
+// For the window pair (i, j): e = L_i - L_j and 1 / (|e|^2 + eps) (Eq. 4);
+// 0 marks a zero denominator (eps = 0 and L_i == L_j), whose weight is 1.
+__device__ __forceinline__ float4 pair_consts(float4 Li, float4 Lj, float eps) {
+  const float ex = Li.x - Lj.x, ey = Li.y - Lj.y, ez = Li.z - Lj.z;
+  const float n = fmaf(ez, ez, fmaf(ey, ey, ex * ex));
+  const float den = n + eps;
+  const float inv = den > 0.0f ? 1.0f / den : 0.0f;
+  return make_float4(ex, ey, ez, inv);
+}
+
+// Eq. 4 weight on i for the pixel offset d = I_p - L_j, clamped to [0, 1].
+__device__ __forceinline__ float pair_alpha(float dx, float dy, float dz, float4 t) {
+  const float g = fmaf(dz, t.z, fmaf(dy, t.y, dx * t.x));
+  return clamp01(g * t.w);
+}
+
+// Residual |d - alpha e|^2 computed from the residual itself (no expansion,
+// so no cancellation when the error is small next to |d|).
+__device__ __forceinline__ float pair_err2(float dx, float dy, float dz, float al, float4 t) {
+  const float rx = fmaf(-al, t.x, dx);
+  const float ry = fmaf(-al, t.y, dy);
+  const float rz = fmaf(-al, t.z, dz);
+  return fmaf(rz, rz, fmaf(ry, ry, rx * rx));
+}
+
+__device__ __forceinline__ void pair_from_index(int p, int& i, int& j) {
+  int jj = (int)((1.0f + sqrtf(1.0f + 8.0f * (float)p)) * 0.5f);
+  while (jj * (jj - 1) / 2 > p) --jj;
+  while ((jj + 1) * jj / 2 <= p) ++jj;
+  j = jj;
+  i = p - jj * (jj - 1) / 2;
+}
+
+// ---------------------------------------------------------------------------
+// Exhaustive search of one strip (Eq. 3 with Eq. 4 over all pairs)
+// ---------------------------------------------------------------------------
+// Candidates in colexicographic order of window offsets (j outer, i < j
+// inner, then (j, j)); the first strict minimum of |residual|^2 wins.
+//
+// Interior windows (all k*k cells present): the degenerate candidate (j, j)
+// with j > 0 never beats (0, j), which precedes it and whose error is at
+// most |I_p - L_j| (alpha >= 0 moves the point along the segment towards
+// the pixel), so only (0, 0) is evaluated.  Border windows evaluate every
+// valid candidate.
+template <int KW, int P, bool BORDER, bool TABLE>
+__device__ __forceinline__ void exh_strip(const float (&ip)[P][3], const float4* __restrict__ win, int lx,
+                                          const float4* __restrict__ tab, float eps, int kw_rt,
+                                          float (&best)[P], int (&code)[P]) {
+  constexpr int kUnrollJ = KW == 3 ? 9 : 1;
+  constexpr int kUnrollI = KW == 3 ? 8 : 2;
+  const int kw = KW > 0 ? KW : kw_rt;
+  const int K2 = kw * kw;
+#pragma unroll
+  for (int q = 0; q < P; ++q) {
+    best[q] = __builtin_inff();
+    code[q] = 0;
+  }
+  if (!BORDER) {
+    const float4 L0 = win[0];
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+      const float dx = ip[q][0] - L0.x, dy = ip[q][1] - L0.y, dz = ip[q][2] - L0.z;
+      best[q] = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+    }
+  }
+#pragma unroll kUnrollJ
+  for (int j = (BORDER ? 0 : 1); j < K2; ++j) {
+    const int jy = j / kw, jx = j - jy * kw;
+    const float4 Lj = win[jy * lx + jx];
+    if (BORDER && Lj.w == 0.0f) continue;
+    float d[P][3];
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+      d[q][0] = ip[q][0] - Lj.x;
+      d[q][1] = ip[q][1] - Lj.y;
+      d[q][2] = ip[q][2] - Lj.z;
+    }
+#pragma unroll kUnrollI
+    for (int i = 0; i < j; ++i) {
+      float4 t;
+      if (TABLE) {
+        t = tab[pair_index(i, j)];
+      } else {
+        const int iy = i / kw, ix = i - iy * kw;
+        const float4 Li = win[iy * lx + ix];
+        if (BORDER && Li.w == 0.0f) continue;
+        t = pair_consts(Li, Lj, eps);
+      }
+      const int cc = i * K2 + j;
+#pragma unroll
+      for (int q = 0; q < P; ++q) {
+        const float al = pair_alpha(d[q][0], d[q][1], d[q][2], t);
+        const float e2 = pair_err2(d[q][0], d[q][1], d[q][2], al, t);
+        const bool lt = e2 < best[q];
+        best[q] = lt ? e2 : best[q];
+        code[q] = lt ? cc : code[q];
+      }
+    }
+    if (BORDER) {
+      const int cc = j * K2 + j;
+#pragma unroll
+      for (int q = 0; q < P; ++q) {
+        const float e2 = fmaf(d[q][2], d[q][2], fmaf(d[q][1], d[q][1], d[q][0] * d[q][0]));
+        const bool lt = e2 < best[q];
+        best[q] = lt ? e2 : best[q];
+        code[q] = lt ? cc : code[q];
+      }
+    }
+  }
+}
+
+// Weight of the winning exhaustive pair, recomputed with the same arithmetic
+// the loop used.
+template <int KW, bool TABLE>
+__device__ __forceinline__ float exh_alpha(const float (&ip)[3], const float4* __restrict__ win, int lx,
+                                           const float4* __restrict__ tab, float eps, int kw_rt, int code) {
+  const int kw = KW > 0 ? KW : kw_rt;
+  const int K2 = kw * kw;
+  const int oi = code / K2, oj = code - oi * K2;
+  if (oi == oj) return 1.0f;
+  const float4 Lj = win[(oj / kw) * lx + (oj % kw)];
+  float4 t;
+  if (TABLE) {
+    t = tab[pair_index(oi, oj)];
+  } else {
+    const float4 Li = win[(oi / kw) * lx + (oi % kw)];
+    t = pair_consts(Li, Lj, eps);
+  }
+  if (t.w == 0.0f) return 1.0f;
+  return pair_alpha(ip[0] - Lj.x, ip[1] - Lj.y, ip[2] - Lj.z, t);
+}
+
+// ---------------------------------------------------------------------------
+// Fast search of one strip (Algorithm 1 with Eq. 5)
+// ---------------------------------------------------------------------------
+// a = first window cell of least colour distance; then every b of the window
+// (b = a included, weight 1) with w_b = |I-L_b| / (|I-L_a| + |I-L_b| + eps),
+// keeping the first b of least error.
+template <int KW, int P, bool BORDER>
+__device__ __forceinline__ void fast_strip(const float (&ip)[P][3], const float4* __restrict__ win, int lx,
+                                           float eps, int kw_rt, float (&best)[P], int (&code)[P],
+                                           float (&alpha)[P]) {
+  constexpr int kUnrollJ = KW == 3 ? 9 : 1;
+  const int kw = KW > 0 ? KW : kw_rt;
+  const int K2 = kw * kw;
+  constexpr bool kKeep = (KW > 0) && (KW * KW * P <= 36);
+  float sd[kKeep ? P : 1][kKeep ? KW * KW : 1];
+  float dmin[P];
+  int ia[P];
+#pragma unroll
+  for (int q = 0; q < P; ++q) {
+    dmin[q] = __builtin_inff();
+    ia[q] = 0;
+  }
+#pragma unroll kUnrollJ
+  for (int j = 0; j < K2; ++j) {
+    const float4 Lj = win[(j / kw) * lx + (j % kw)];
+    if (BORDER && Lj.w == 0.0f) continue;
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+      const float dx = ip[q][0] - Lj.x, dy = ip[q][1] - Lj.y, dz = ip[q][2] - Lj.z;
+      const float D = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+      if constexpr (kKeep) sd[q][j] = __builtin_amdgcn_sqrtf(D);
+      const bool lt = D < dmin[q];
+      dmin[q] = lt ? D : dmin[q];
+      ia[q] = lt ? j : ia[q];
+    }
+  }
+  float La[P][3], sa[P], omb[P];
+#pragma unroll
+  for (int q = 0; q < P; ++q) {
+    const float4 A = win[(ia[q] / kw) * lx + (ia[q] % kw)];
+    La[q][0] = A.x;
+    La[q][1] = A.y;
+    La[q][2] = A.z;
+    sa[q] = __builtin_amdgcn_sqrtf(dmin[q]);
+    best[q] = dmin[q];
+    code[q] = ia[q] * K2 + ia[q];
+    omb[q] = 1.0f;
+  }
+#pragma unroll kUnrollJ
+  for (int b = 0; b < K2; ++b) {
+    const float4 Lb = win[(b / kw) * lx + (b % kw)];
+    if (BORDER && Lb.w == 0.0f) continue;
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+      float sb;
+      if constexpr (kKeep) {
+        sb = sd[q][b];
+      } else {
+        const float dx = ip[q][0] - Lb.x, dy = ip[q][1] - Lb.y, dz = ip[q][2] - Lb.z;
+        sb = __builtin_amdgcn_sqrtf(fmaf(dz, dz, fmaf(dy, dy, dx * dx)));
+      }
+      const float den = (sa[q] + sb) + eps;
+      const float om = sb * __builtin_amdgcn_rcpf(den);
+      const float om1 = 1.0f - om;
+      // residual = om L_a + (1 - om) L_b - I, negated
+      const float tx = fmaf(-om, La[q][0], ip[q][0]);
+      const float ty = fmaf(-om, La[q][1], ip[q][1]);
+      const float tz = fmaf(-om, La[q][2], ip[q][2]);
+      const float rx = fmaf(-om1, Lb.x, tx);
+      const float ry = fmaf(-om1, Lb.y, ty);
+      const float rz = fmaf(-om1, Lb.z, tz);
+      const float e2 = fmaf(rz, rz, fmaf(ry, ry, rx * rx));
+      const bool lt = e2 < best[q];
+      best[q] = lt ? e2 : best[q];
+      code[q] = lt ? ia[q] * K2 + b : code[q];
+      omb[q] = lt ? om : omb[q];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < P; ++q) {
+    const int ob = code[q] - ia[q] * K2;
+    alpha[q] = (ob == ia[q]) ? 1.0f : omb[q];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// One tile of search (+ apply when FUSED)
+// ---------------------------------------------------------------------------
+enum { MODE_EXH = 0, MODE_FAST = 1 };
+
+// LDS float4 words one search tile needs.
+__host__ __device__ inline int search_tile_words(int tqy, int tqx, int k, int mode, bool fused, bool table) {
+  const int r = k / 2;
+  const int ncell = (tqy + 2 * r) * (tqx + 2 * r);
+  int words = ncell * (fused ? 2 : 1);
+  if (mode == MODE_EXH && table) words += tqy * tqx * (n_pairs(k * k) + 1);
+  return words;
+}
+
+template <typename T>
+__device__ __forceinline__ void stage_lr(const ImgDesc& d, int qy0, int qx0, int R, int ly, int lx,
+                                         float4* sL, float4* sT) {
+  const T* __restrict__ L = static_cast<const T*>(d.L);
+  const T* __restrict__ TL = static_cast<const T*>(d.T);
+  const int ncell = ly * lx;
+  for (int c = threadIdx.x; c < ncell; c += kThreads) {
+    const int oy = c / lx;
+    const int cy = qy0 - R + oy, cx = qx0 - R + (c - oy * lx);
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f), tv = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (cy >= 0 && cy < d.h && cx >= 0 && cx < d.w) {
+      if (sL) {
+        const T* q = L + (int64_t)cy * d.L_stride + (int64_t)cx * 3;
+        v = make_float4(to_f<T>(q[0]), to_f<T>(q[1]), to_f<T>(q[2]), 1.0f);
+      }
+      if (sT) {
+        const T* q = TL + (int64_t)cy * d.T_stride + (int64_t)cx * d.C;
+        float tt[4] = {0.f, 0.f, 0.f, 0.f};
+        for (int ch = 0; ch < d.C; ++ch) tt[ch] = to_f<T>(q[ch]);
+        tv = make_float4(tt[0], tt[1], tt[2], tt[3]);
+      }
+    }
+    if (sL) sL[c] = v;
+    if (sT) sT[c] = tv;
+  }
+}
+
+template <int KW, int P, int MODE, typename T, bool FUSED, bool TABLE>
+__device__ __forceinline__ void search_tile(const ImgDesc& d, int ty, int tx, float eps, float4* smem) {
+  const int kw = KW > 0 ? KW : d.k;
+  const int R = kw / 2;
+  const int K2 = kw * kw;
+  const int s = d.s;
+  const int tqy = d.tqy, tqx = d.tqx;
+  const int qy0 = ty * tqy, qx0 = tx * tqx;
+  const int ly = tqy + 2 * R, lx = tqx + 2 * R;
+  const int ncell = ly * lx;
+  float4* sL = smem;
+  float4* sT = FUSED ? smem + ncell : nullptr;
+  float4* sTab = smem + (FUSED ? 2 : 1) * ncell;
+  const int tstride = n_pairs(K2) + 1;
+
+  stage_lr<T>(d, qy0, qx0, R, ly, lx, sL, sT);
+  __syncthreads();
+  if (MODE == MODE_EXH && TABLE) {
+    const int np = n_pairs(K2);
+    const int total = tqy * tqx * np;
+    for (int e = threadIdx.x; e < total; e += kThreads) {
+      const int c = e / np, pr = e - c * np;
+      int i, j;
+      pair_from_index(pr, i, j);
+      const int cy = c / tqx, cx = c - cy * tqx;
+      const float4 Li = sL[(cy + i / kw) * lx + cx + i % kw];
+      const float4 Lj = sL[(cy + j / kw) * lx + cx + j % kw];
+      sTab[c * tstride + pr] = pair_consts(Li, Lj, eps);
+    }
+    __syncthreads();
+  }
+
+  const int rows = tqy * s, cols = tqx * s;
+  const int spr = cols / P;
+  const int nstrips = rows * spr;
+  const bool interior = (qy0 - R >= 0) && (qy0 + tqy + R <= d.h) && (qx0 - R >= 0) &&
+                        (qx0 + tqx + R <= d.w) && ((qy0 + tqy) * s <= d.H) && ((qx0 + tqx) * s <= d.W);
+  const bool vecI = (d.vec & VEC_I) != 0, vecTh = (d.vec & VEC_THETA) != 0, vecT = (d.vec & VEC_T) != 0;
+  const T* __restrict__ Ig = static_cast<const T*>(d.I);
+
+  for (int t = threadIdx.x; t < nstrips; t += kThreads) {
+    const int ry = t / spr;
+    const int rx = (t - ry * spr) * P;
+    const int y = qy0 * s + ry, x = qx0 * s + rx;
+    if (y >= d.H || x >= d.W) continue;
+    const int cy = ry / s, cx = rx / s;
+    const float4* win = sL + cy * lx + cx;
+    const float4* tab = sTab + (cy * tqx + cx) * tstride;
+    const bool full = interior || (x + P <= d.W);
+
+    float ip[P][3];
+    load_strip3<T, P>(Ig + (int64_t)y * d.I_stride, x, d.W, vecI, full, ip);
+    float best[P], al[P];
+    int code[P];
+    if (MODE == MODE_EXH) {
+      if (interior) {
+        exh_strip<KW, P, false, TABLE>(ip, win, lx, tab, eps, kw, best, code);
+#pragma unroll
+        for (int q = 0; q < P; ++q) al[q] = exh_alpha<KW, TABLE>(ip[q], win, lx, tab, eps, kw, code[q]);
+      } else {
+        exh_strip<KW, P, true, false>(ip, win, lx, tab, eps, kw, best, code);
+#pragma unroll
+        for (int q = 0; q < P; ++q) al[q] = exh_alpha<KW, false>(ip[q], win, lx, tab, eps, kw, code[q]);
+      }
+    } else {
+      if (interior)
+        fast_strip<KW, P, false>(ip, win, lx, eps, kw, best, code, al);
+      else
+        fast_strip<KW, P, true>(ip, win, lx, eps, kw, best, code, al);
+    }
+    float e[P];
+#pragma unroll
+    for (int q = 0; q < P; ++q) e[q] = __builtin_amdgcn_sqrtf(best[q]);
+    const int64_t to = (int64_t)y * d.th_stride;
+    store_theta<P>(d.code ? d.code + to : nullptr, d.alpha ? d.alpha + to : nullptr, d.err ? d.err + to : nullptr,
+                   x, d.W, vecTh, full, code, al, e);
+    if (FUSED) {
+      float o[P][4];
+#pragma unroll
+      for (int q = 0; q < P; ++q) {
+        const int oa = code[q] / K2, ob = code[q] - oa * K2;
+        const float4 Ta = sT[(cy + oa / kw) * lx + cx + oa % kw];
+        const float4 Tb = sT[(cy + ob / kw) * lx + cx + ob % kw];
+        o[q][0] = fmaf(al[q], Ta.x - Tb.x, Tb.x);
+        o[q][1] = fmaf(al[q], Ta.y - Tb.y, Tb.y);
+        o[q][2] = fmaf(al[q], Ta.z - Tb.z, Tb.z);
+        o[q][3] = fmaf(al[q], Ta.w - Tb.w, Tb.w);
+      }
+      store_out<T, P>(static_cast<T*>(d.That) + (int64_t)y * d.That_stride, x, d.W, d.C, vecT, full, o);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// One tile of apply (Eq. 1)
+// ---------------------------------------------------------------------------
+template <int KW, int P, typename T>
+__device__ __forceinline__ void apply_tile(const ImgDesc& d, int ty, int tx, float4* smem) {
+  const int kw = KW > 0 ? KW : d.k;
+  const int R = kw / 2;
+  const int K2 = kw * kw;
+  const int s = d.s;
+  const int tqy = d.tqy, tqx = d.tqx;
+  const int qy0 = ty * tqy, qx0 = tx * tqx;
+  const int ly = tqy + 2 * R, lx = tqx + 2 * R;
+  float4* sT = smem;
+  stage_lr<T>(d, qy0, qx0, R, ly, lx, nullptr, sT);
+  __syncthreads();
+
+  const int rows = tqy * s, cols = tqx * s;
+  const int spr = cols / P;
+  const int nstrips = rows * spr;
+  const bool interior = ((qy0 + tqy) * s <= d.H) && ((qx0 + tqx) * s <= d.W);
+  const bool vecTh = (d.vec & VEC_THETA) != 0, vecT = (d.vec & VEC_T) != 0;
+  const int maxcode = K2 * K2 - 1;
+  for (int t = threadIdx.x; t < nstrips; t += kThreads) {
+    const int ry = t / spr;
+    const int rx = (t - ry * spr) * P;
+    const int y = qy0 * s + ry, x = qx0 * s + rx;
+    if (y >= d.H || x >= d.W) continue;
+    const int cy = ry / s, cx = rx / s;
+    const bool full = interior || (x + P <= d.W);
+    const int64_t to = (int64_t)y * d.th_stride + x;
+    int code[P];
+    float al[P];
+    bool done = false;
+    if constexpr (P == 4) {
+      if (vecTh && full) {
+        const uint2 c = *reinterpret_cast<const uint2*>(d.code + to);
+        const float4 a4 = *reinterpret_cast<const float4*>(d.alpha + to);
+        code[0] = c.x & 0xffff;
+        code[1] = c.x >> 16;
+        code[2] = c.y & 0xffff;
+        code[3] = c.y >> 16;
+        al[0] = a4.x;
+        al[1] = a4.y;
+        al[2] = a4.z;
+        al[3] = a4.w;
+        done = true;
+      }
+    }
+    if (!done) {
+#pragma unroll
+      for (int q = 0; q < P; ++q) {
+        const bool ok = full || (x + q < d.W);
+        code[q] = ok ? d.code[to + q] : 0;
+        al[q] = ok ? d.alpha[to + q] : 0.0f;
+      }
+    }
+    float o[P][4];
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+      const int cd = min(code[q], maxcode);
+      const int oa = cd / K2, ob = cd - oa * K2;
+      const float4 Ta = sT[(cy + oa / kw) * lx + cx + oa % kw];
+      const float4 Tb = sT[(cy + ob / kw) * lx + cx + ob % kw];
+      o[q][0] = fmaf(al[q], Ta.x - Tb.x, Tb.x);
+      o[q][1] = fmaf(al[q], Ta.y - Tb.y, Tb.y);
+      o[q][2] = fmaf(al[q], Ta.z - Tb.z, Tb.z);
+      o[q][3] = fmaf(al[q], Ta.w - Tb.w, Tb.w);
+    }
+    store_out<T, P>(static_cast<T*>(d.That) + (int64_t)y * d.That_stride, x, d.W, d.C, vecT, full, o);
+  }
+}
+
+}  // namespace glu

@@ -1,0 +1,52 @@
+// Host-side helpers of libglu: error reporting, argument validation and the
+// tile-shape choice shared by every entry point.
+#pragma once
+
+#include <cstdarg>
+#include <cstdio>
+#include <string>
+
+#include "glu_internal.h"
+
+namespace glu {
+
+// Records a failure for glu_last_error() and returns the status.
+glu_status fail(glu_status st, const char* fmt, ...);
+// Clears the calling thread's last error.
+void clear_error();
+
+// Maps a HIP error to GLU_ERR_HIP with context.
+glu_status hip_fail(hipError_t e, const char* what);
+
+inline size_t dtype_size(glu_dtype t) { return t == GLU_F16 ? 2 : 4; }
+inline bool dtype_ok(int t) { return t == GLU_F32 || t == GLU_F16; }
+
+// Validation of one image descriptor: non-NULL (unless empty), channel
+// count, stride, dtype and element alignment.
+glu_status check_image(const glu_image* im, const char* name, int channels_lo, int channels_hi,
+                       bool allow_f16 = true);
+glu_status check_params(const glu_params* p);
+glu_status check_theta(const glu_theta* th, int H, int W, bool need_buffers);
+
+inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
+
+// Tile shape of a search / apply launch.
+struct TileChoice {
+  int P;    // pixels per strip (4 when 4 divides s, else 1)
+  int tqy;  // tile height in LR centres
+  int tqx;  // tile width in LR centres
+};
+
+// Default tile: about 64 HR columns by enough rows for 256 strips, shrunk
+// until the LDS of the tile fits.  `variant` selects alternatives for the
+// autotuner (0 = default).
+TileChoice choose_tile(int s, int k, int mode, bool fused, bool table, int variant);
+int n_tile_variants();
+
+// Fills the image descriptor fields common to search / apply launches.
+void fill_tiles(ImgDesc& d, const TileChoice& tc);
+
+// Kernel variant index used by the batched dispatcher.
+int kernel_variant(int k, int P, int mode, int dtype);
+
+}  // namespace glu

@@ -1,0 +1,229 @@
+"""Python binding of libglu: torch tensors in, torch tensors out.
+
+Argument marshalling only: every step runs in the HIP kernels behind the C
+ABI of include/glu.h.  Tensors must live on the GPU; images are (H, W, C)
+with the channel axis innermost (rows may be padded).  Theta is returned as a
+``Theta`` pair of (H, W) tensors: ``code`` (int16 holding the uint16 codes)
+and ``alpha`` (float32).  All calls run on torch's current stream.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib as L
+
+EPS = 1e-3  # Eq. 4 regulariser (Sec. 3.1)
+TAU = 30.0 / 255.0  # error threshold of Algorithm 2 (Sec. 5.2)
+N_ITER = 3  # iterations of Algorithm 2 (Sec. 5.2)
+
+_MODES = {"exhaustive": L.GLU_SEARCH_EXHAUSTIVE, "fast": L.GLU_SEARCH_FAST}
+
+
+@dataclass
+class Theta:
+    code: torch.Tensor  # (H, W) int16 view of the uint16 codes
+    alpha: torch.Tensor  # (H, W) float32
+
+    @property
+    def shape(self):
+        return tuple(self.code.shape)
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dtype_code(t: torch.Tensor) -> int:
+    if t.dtype == torch.float32:
+        return L.GLU_F32
+    if t.dtype == torch.float16:
+        return L.GLU_F16
+    raise TypeError("images must be float32 or float16, got %s" % t.dtype)
+
+
+def _img(t: torch.Tensor, name: str) -> L.glu_image:
+    if not isinstance(t, torch.Tensor) or t.dim() != 3:
+        raise ValueError("%s must be an (H, W, C) tensor" % name)
+    if not t.is_cuda:
+        raise ValueError("%s must be a GPU tensor" % name)
+    H, W, Cn = t.shape
+    if H * W > 0 and not (t.stride(2) == 1 and (W <= 1 or t.stride(1) == Cn)):
+        raise ValueError("%s rows must be dense (channels innermost, pixels adjacent)" % name)
+    stride = t.stride(0) if H > 1 else W * Cn
+    return L.glu_image(t.data_ptr() if t.numel() else None, H, W, Cn, max(stride, W * Cn), _dtype_code(t))
+
+
+def _theta(th: Theta) -> L.glu_theta:
+    code, alpha = th.code, th.alpha
+    if code.dtype != torch.int16 or alpha.dtype != torch.float32:
+        raise TypeError("theta must be (int16 code, float32 alpha)")
+    if code.shape != alpha.shape or code.dim() != 2:
+        raise ValueError("theta code and alpha must both be (H, W)")
+    if code.stride() != alpha.stride() or (code.numel() and code.stride(1) != 1):
+        raise ValueError("theta code and alpha must share a row-major layout")
+    H, W = code.shape
+    stride = code.stride(0) if H > 1 else W
+    return L.glu_theta(
+        code.data_ptr() if code.numel() else None, alpha.data_ptr() if alpha.numel() else None, H, W, max(stride, W)
+    )
+
+
+def _params(s: int, k: int, eps: float, mode: str = "exhaustive") -> L.glu_params:
+    if mode not in _MODES:
+        raise ValueError("mode must be 'exhaustive' or 'fast'")
+    return L.glu_params(int(s), int(k), float(eps), _MODES[mode], 0)
+
+
+def lr_shape(H: int, W: int, s: int):
+    return (-(-H // s), -(-W // s))
+
+
+def empty_theta(H: int, W: int, device="cuda") -> Theta:
+    return Theta(
+        torch.empty((H, W), dtype=torch.int16, device=device), torch.empty((H, W), dtype=torch.float32, device=device)
+    )
+
+
+def downsample(I: torch.Tensor, s: int, mode: str = "point") -> torch.Tensor:
+    """Regular-grid (point) or box downsampling of I to ceil(H/s) x ceil(W/s)."""
+    h, w = lr_shape(I.shape[0], I.shape[1], s)
+    out = torch.empty((h, w, I.shape[2]), dtype=I.dtype, device=I.device)
+    m = {"point": L.GLU_DOWN_POINT, "box": L.GLU_DOWN_BOX}[mode]
+    lib = L.load()
+    L.check(lib.glu_downsample(C.byref(_img(I, "I")), C.byref(_img(out, "I_low")), int(s), m, _stream()))
+    return out
+
+
+def search(I, I_low, s, k=3, eps=EPS, mode="exhaustive", return_err=False, theta: Theta | None = None, err=None):
+    """Per-pixel (a, b, alpha) search; returns Theta (and E when return_err)."""
+    H, W = I.shape[:2]
+    theta = theta if theta is not None else empty_theta(H, W, I.device)
+    if return_err and err is None:
+        err = torch.empty((H, W), dtype=torch.float32, device=I.device)
+    p = _params(s, k, eps, mode)
+    lib = L.load()
+    L.check(
+        lib.glu_search(
+            C.byref(_img(I, "I")),
+            C.byref(_img(I_low, "I_low")),
+            C.byref(p),
+            C.byref(_theta(theta)),
+            C.c_void_p(err.data_ptr() if err is not None and err.numel() else None),
+            _stream(),
+        )
+    )
+    return (theta, err) if return_err else theta
+
+
+def apply(theta: Theta, T_low: torch.Tensor, s: int, k: int = 3, out: torch.Tensor | None = None):
+    """Eq. 1 with a given Theta."""
+    H, W = theta.shape
+    if out is None:
+        out = torch.empty((H, W, T_low.shape[2]), dtype=T_low.dtype, device=T_low.device)
+    p = _params(s, k, EPS)
+    lib = L.load()
+    L.check(
+        lib.glu_apply(
+            C.byref(_theta(theta)), C.byref(_img(T_low, "T_low")), C.byref(p), C.byref(_img(out, "T_hat")), _stream()
+        )
+    )
+    return out
+
+
+def search_apply(
+    I, I_low, T_low, s, k=3, eps=EPS, mode="exhaustive", store_theta=True, return_err=False, theta=None, out=None,
+    err=None,
+):
+    """Fused search + apply; returns (T_hat, Theta or None[, E])."""
+    H, W = I.shape[:2]
+    if store_theta and theta is None:
+        theta = empty_theta(H, W, I.device)
+    if out is None:
+        out = torch.empty((H, W, T_low.shape[2]), dtype=T_low.dtype, device=I.device)
+    if return_err and err is None:
+        err = torch.empty((H, W), dtype=torch.float32, device=I.device)
+    p = _params(s, k, eps, mode)
+    lib = L.load()
+    th = C.byref(_theta(theta)) if theta is not None else None
+    L.check(
+        lib.glu_search_apply(
+            C.byref(_img(I, "I")),
+            C.byref(_img(I_low, "I_low")),
+            C.byref(_img(T_low, "T_low")),
+            C.byref(p),
+            th,
+            C.c_void_p(err.data_ptr() if err is not None and err.numel() else None),
+            C.byref(_img(out, "T_hat")),
+            _stream(),
+        )
+    )
+    return (out, theta, err) if return_err else (out, theta)
+
+
+def theta_expand(theta: Theta, s: int, k: int = 3):
+    """Absolute LR linear indices (a, b), int64 (H, W): the paper's 3 x H x W form with alpha."""
+    H, W = theta.shape
+    a = torch.empty((H, W), dtype=torch.int64, device=theta.code.device)
+    b = torch.empty((H, W), dtype=torch.int64, device=theta.code.device)
+    p = _params(s, k, EPS)
+    lib = L.load()
+    L.check(
+        lib.glu_theta_expand(
+            C.byref(_theta(theta)), C.byref(p), C.c_void_p(a.data_ptr() if a.numel() else None),
+            C.c_void_p(b.data_ptr() if b.numel() else None), _stream()
+        )
+    )
+    return a, b
+
+
+def apply_backward(theta: Theta, T_low, grad_T_hat, s, k=3, need_T_low=True, need_alpha=True):
+    """Gradients of Eq. 1 (indices fixed): returns (grad_T_low or None, grad_alpha or None)."""
+    H, W = theta.shape
+    gT = torch.empty(T_low.shape, dtype=torch.float32, device=T_low.device) if need_T_low else None
+    ga = torch.empty((H, W), dtype=torch.float32, device=T_low.device) if need_alpha else None
+    p = _params(s, k, EPS)
+    lib = L.load()
+    L.check(
+        lib.glu_apply_backward(
+            C.byref(_theta(theta)),
+            C.byref(_img(T_low, "T_low")),
+            C.byref(p),
+            C.byref(_img(grad_T_hat, "grad_T_hat")),
+            C.byref(_img(gT, "grad_T_low")) if gT is not None else None,
+            C.c_void_p(ga.data_ptr() if ga is not None and ga.numel() else None),
+            _stream(),
+        )
+    )
+    return gT, ga
+
+
+class GluApply(torch.autograd.Function):
+    """Eq. 1 as an autograd function of (alpha, T_low); the codes are constant.
+
+    forward(alpha, T_low, code, s, k) -> T_hat.  The backward is the
+    hand-written deterministic gather of glu_apply_backward.
+    """
+
+    @staticmethod
+    def forward(ctx, alpha, T_low, code, s, k=3):
+        th = Theta(code, alpha.contiguous())
+        out = apply(th, T_low.contiguous(), s, k)
+        ctx.save_for_backward(code, th.alpha, T_low)
+        ctx.s, ctx.k = s, k
+        return out
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        code, alpha, T_low = ctx.saved_tensors
+        g = grad_out.contiguous().float()
+        gT, ga = apply_backward(
+            Theta(code, alpha), T_low, g, ctx.s, ctx.k, ctx.needs_input_grad[1], ctx.needs_input_grad[0]
+        )
+        return ga, gT, None, None, None
+
+
+def glu_apply_autograd(alpha, T_low, code, s, k=3):
+    return GluApply.apply(alpha, T_low, code, s, k)

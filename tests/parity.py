@@ -1,0 +1,152 @@
+"""Parity protocol between the GPU path (float32) and the float64 oracle.
+
+Per pixel (exhaustive mode):
+  1. GPU pair == oracle pair: |alpha_gpu - alpha_or| <= 1e-5.
+  2. otherwise the choice must be a near-tie: the oracle evaluates the GPU's
+     pair (err') and requires err' - err_or <= 1e-6 (Euclidean, not
+     squared); alpha is then checked against the oracle's weight for the
+     GPU's pair.
+Fast mode applies rule 2 first to the anchor (colour-distance gap), then to
+b given the GPU's anchor.  E (when returned) must match the oracle's error
+of the GPU's pair to 1e-6, and T_hat the oracle's Eq. 1 with the GPU's
+pair and the oracle's weight for it to 1e-5 (float32) or one half-precision
+ulp + 1e-5 (float16).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+import oracle as O
+
+ALPHA_TOL = 1e-5
+TIE_TOL = 1e-6
+T_TOL = 1e-5
+E_TOL = 1e-6
+
+
+def decode_codes(code, H, W, s, k, pixels):
+    """Absolute LR indices (a, b) from uint16 codes (format of include/glu.h)."""
+    w = -(-W // s)
+    h = -(-H // s)
+    code = np.asarray(code).astype(np.int64) & 0xFFFF
+    K2 = k * k
+    r = k // 2
+    ys, xs = np.divmod(np.asarray(pixels, dtype=np.int64), W)
+    cd = code.reshape(-1)[pixels]
+    oa, ob = np.divmod(cd, K2)
+    qy, qx = ys // s, xs // s
+    a = (qy + oa // k - r) * w + (qx + oa % k - r)
+    b = (qy + ob // k - r) * w + (qx + ob % k - r)
+    def inside(o):
+        cy, cx = qy + o // k - r, qx + o % k - r
+        return (o < K2) & (cy >= 0) & (cy < h) & (cx >= 0) & (cx < w)
+
+    valid_a = inside(oa)
+    valid_b = inside(ob)
+    return a, b, valid_a & valid_b
+
+
+def _in_window(a, pixels, W, s, k, h, w):
+    ys, xs = np.divmod(np.asarray(pixels, dtype=np.int64), W)
+    qy, qx = ys // s, xs // s
+    ay, ax = np.divmod(a, w)
+    r = k // 2
+    return (np.abs(ay - qy) <= r) & (np.abs(ax - qx) <= r) & (ay >= 0) & (ay < h) & (ax >= 0) & (ax < w)
+
+
+class ParityReport(dict):
+    pass
+
+
+def check_search(I, L, s, k, eps, mode, code, alpha, err=None, pixels=None, T_low=None, T_hat=None,
+                 out_dtype=np.float32):
+    """Runs the oracle on `pixels` (default all) and checks the GPU outputs.
+
+    I, L, T_low: host arrays of the exact values the GPU consumed.
+    code, alpha, err, T_hat: host copies of the GPU outputs (full images).
+    Returns a report dict; raises AssertionError on a violation.
+    """
+    I = np.asarray(I)
+    H, W = I.shape[:2]
+    h, w = L.shape[:2]
+    if pixels is None:
+        pixels = np.arange(H * W, dtype=np.int64)
+    pixels = np.asarray(pixels, dtype=np.int64)
+    rep = ParityReport(n=int(pixels.size), near_ties=0)
+    if pixels.size == 0:
+        return rep
+    a_g, b_g, ok = decode_codes(code, H, W, s, k, pixels)
+    assert ok.all(), "GPU codes point outside the LR image at %d pixels" % int((~ok).sum())
+    assert _in_window(a_g, pixels, W, s, k, h, w).all() and _in_window(b_g, pixels, W, s, k, h, w).all()
+    al_g = np.asarray(alpha, dtype=np.float64).reshape(-1)[pixels]
+    ref = O.search(I, L, s, k, eps, mode, pixels=pixels)
+    if mode == "exhaustive":
+        assert np.all(a_g <= b_g), "exhaustive codes must have a <= b"
+        same = (a_g == ref.a) & (b_g == ref.b)
+        al_ref = np.where(same, ref.alpha, 0.0)
+        e_ref = ref.err.copy()
+        if (~same).any():
+            idx = np.flatnonzero(~same)
+            al2, e2 = O.eval_pairs_exhaustive(I, L, pixels[idx], a_g[idx], b_g[idx], eps)
+            gap = e2 - ref.err[idx]
+            bad = gap > TIE_TOL
+            assert not bad.any(), (
+                "non-tie pair mismatch at %d pixels, worst gap %.3g (pixel %d)"
+                % (int(bad.sum()), float(gap.max()), int(pixels[idx][np.argmax(gap)]))
+            )
+            al_ref[idx] = al2
+            e_ref[idx] = e2
+            rep["near_ties"] = int(idx.size)
+    else:
+        # anchor first: the GPU anchor must be (nearly) as close as the oracle's
+        Lf = np.asarray(L, dtype=np.float64).reshape(-1, 3)
+        ys, xs = np.divmod(pixels, W)
+        Ip = np.asarray(I, dtype=np.float64)[ys, xs]
+        da_g = np.linalg.norm(Ip - Lf[a_g], axis=1)
+        da_o = np.linalg.norm(Ip - Lf[ref.a], axis=1)
+        gap_a = da_g - da_o
+        assert not (gap_a > TIE_TOL).any(), "non-tie anchor mismatch, worst gap %.3g" % float(gap_a.max())
+        diff_a = a_g != ref.a
+        if diff_a.any():
+            idx = np.flatnonzero(diff_a)
+            r2 = O.search_fast_given_anchor(I, L, s, k, eps, pixels[idx], a_g[idx])
+            for f in ("b", "alpha", "err"):
+                getattr(ref, f)[idx] = getattr(r2, f)[...]
+            ref.a[idx] = a_g[idx]
+        same = b_g == ref.b
+        al_ref = np.where(same, ref.alpha, 0.0)
+        e_ref = ref.err.copy()
+        if (~same).any():
+            idx = np.flatnonzero(~same)
+            al2, e2 = O.eval_pairs_fast(I, L, pixels[idx], a_g[idx], b_g[idx], eps)
+            gap = e2 - ref.err[idx]
+            bad = gap > TIE_TOL
+            assert not bad.any(), (
+                "non-tie partner mismatch at %d pixels, worst gap %.3g" % (int(bad.sum()), float(gap.max()))
+            )
+            al_ref[idx] = al2
+            e_ref[idx] = e2
+        rep["near_ties"] = int((~same).sum() + diff_a.sum())
+    da = np.abs(al_g - al_ref)
+    assert da.max() <= ALPHA_TOL, "alpha error %.3g > %.1g at pixel %d" % (
+        float(da.max()), ALPHA_TOL, int(pixels[np.argmax(da)]))
+    assert np.all((al_g >= 0) & (al_g <= 1))
+    rep["alpha_max_err"] = float(da.max())
+    if err is not None:
+        e_g = np.asarray(err, dtype=np.float64).reshape(-1)[pixels]
+        de = np.abs(e_g - e_ref)
+        assert de.max() <= E_TOL, "E error %.3g at pixel %d" % (float(de.max()), int(pixels[np.argmax(de)]))
+        rep["err_max_err"] = float(de.max())
+    if T_hat is not None:
+        Cn = T_low.shape[2]
+        ref_T = O.apply(a_g, b_g, al_ref, T_low)
+        got = np.asarray(T_hat, dtype=np.float64).reshape(-1, Cn)[pixels]
+        dT = np.abs(got - ref_T)
+        if out_dtype == np.float16:
+            tol = np.abs(np.spacing(ref_T.astype(np.float16))).astype(np.float64) + T_TOL
+            assert np.all(dT <= tol), "T_hat fp16 error %.3g" % float(dT.max())
+        else:
+            assert dT.max() <= T_TOL, "T_hat error %.3g at pixel %d" % (
+                float(dT.max()), int(pixels[np.argmax(dT.max(axis=1))]))
+        rep["T_max_err"] = float(dT.max())
+    return rep

@@ -1,0 +1,121 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function include/glu.h declares, and rejects invalid arguments before
+enqueuing anything."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2307_09582_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    hdr = open(os.path.join(ROOT, "include", "glu.h")).read()
+    hdr = re.sub(r"/\*.*?\*/", "", hdr, flags=re.S)
+    names = re.findall(r"\b(glu_[a-z0-9_]+)\s*\(", hdr)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = L.load()
+    names = _declared_functions()
+    assert len(names) >= 18
+    for n in names:
+        assert hasattr(lib, n), "missing export " + n
+    assert set(names) == set(L._SIGS), "binding signatures out of sync with glu.h"
+
+
+def test_status_strings():
+    lib = L.load()
+    for code, name in L.STATUS_NAMES.items():
+        assert lib.glu_status_string(code).decode() == name
+    assert lib.glu_version().decode().startswith("glu-mi355x")
+
+
+def _img(ptr=0x1000, H=8, W=8, Cn=3, stride=None, dt=L.GLU_F32):
+    return L.glu_image(ptr, H, W, Cn, stride if stride is not None else W * Cn, dt)
+
+
+def _params(s=4, k=3, eps=1e-3, mode=0, flags=0):
+    return L.glu_params(s, k, eps, mode, flags)
+
+
+def _theta(H=8, W=8, code=0x2000, alpha=0x3000):
+    return L.glu_theta(code, alpha, H, W, W)
+
+
+def _search(I, Il, p, th):
+    lib = L.load()
+    return lib.glu_search(
+        C.byref(I) if I is not None else None,
+        C.byref(Il) if Il is not None else None,
+        C.byref(p) if p is not None else None,
+        C.byref(th) if th is not None else None,
+        None,
+        None,
+    )
+
+
+@pytest.mark.parametrize(
+    "kw,expect",
+    [
+        (dict(p=None), 1),
+        (dict(I=None), 1),
+        (dict(p=_params(s=0)), 4),
+        (dict(p=_params(k=4)), 4),
+        (dict(p=_params(k=17)), 4),
+        (dict(p=_params(eps=-1.0)), 4),
+        (dict(p=_params(eps=float("nan"))), 4),
+        (dict(p=_params(mode=7)), 4),
+        (dict(p=_params(flags=1)), 4),
+        (dict(I=_img(Cn=4)), 2),
+        (dict(Il=_img(H=3, W=2)), 2),
+        (dict(Il=_img(H=2, W=2, dt=L.GLU_F16)), 3),
+        (dict(I=_img(dt=9)), 3),
+        (dict(I=_img(ptr=0x1001)), 5),
+        (dict(I=_img(stride=5)), 2),
+        (dict(th=_theta(H=7)), 2),
+        (dict(th=_theta(code=0)), 1),
+        (dict(I=_img(ptr=0)), 1),
+    ],
+)
+def test_search_validation(kw, expect):
+    args = dict(I=_img(), Il=_img(H=2, W=2), p=_params(), th=_theta())
+    args.update(kw)
+    st = _search(args["I"], args["Il"], args["p"], args["th"])
+    assert st == expect, L.load().glu_last_error()
+    assert L.load().glu_last_error().decode().startswith(L.STATUS_NAMES[expect])
+
+
+def test_apply_validation():
+    lib = L.load()
+    th = _theta()
+    p = _params()
+    # T_low with the wrong LR size
+    st = lib.glu_apply(C.byref(th), C.byref(_img(H=3, W=2, Cn=1)), C.byref(p), C.byref(_img(Cn=1)), None)
+    assert st == 2
+    # channel counts differ
+    st = lib.glu_apply(C.byref(th), C.byref(_img(H=2, W=2, Cn=1)), C.byref(p), C.byref(_img(Cn=2)), None)
+    assert st == 2
+    # more than 4 channels
+    st = lib.glu_apply(C.byref(th), C.byref(_img(H=2, W=2, Cn=5)), C.byref(p), C.byref(_img(Cn=5)), None)
+    assert st == 2
+
+
+def test_downsample_and_expand_validation():
+    lib = L.load()
+    assert lib.glu_downsample(C.byref(_img()), C.byref(_img(H=2, W=2)), 0, 0, None) == 4
+    assert lib.glu_downsample(C.byref(_img()), C.byref(_img(H=2, W=2)), 4, 5, None) == 4
+    assert lib.glu_downsample(C.byref(_img()), C.byref(_img(H=3, W=2)), 4, 0, None) == 2
+    th = _theta()
+    assert lib.glu_theta_expand(C.byref(th), C.byref(_params()), None, None, None) == 1
+    assert lib.glu_theta_expand(C.byref(th), C.byref(_params()), 0x1004, 0x2000, None) == 5
+
+
+def test_empty_images_return_ok_without_launch():
+    # zero pixels: valid arguments, nothing to do, no HIP call is made
+    st = _search(_img(ptr=0, H=0, W=5), _img(ptr=0, H=0, W=2), _params(), _theta(H=0, W=5, code=0, alpha=0))
+    assert st == 0

@@ -1,0 +1,216 @@
+"""GPU parity of glu_search / glu_apply / glu_search_apply against the oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import synth
+from tests.gpu_util import dev, host, log_case, need_gpu
+from tests.parity import check_search
+
+pytestmark = pytest.mark.gpu
+
+
+def _glu():
+    need_gpu()
+    import paper_2307_09582_amd as glu
+
+    return glu
+
+
+def _inputs(H, W, s, seed, n_cells, n_dots, dot_px=(1, 3), down="point", C=3, lr_op="f1"):
+    I = synth.voronoi(H, W, n_cells=n_cells, n_dots=n_dots, dot_px=dot_px, sigma=0.01, seed=seed)
+    if down == "point":
+        L = O.downsample_point(I, s)
+    else:
+        L = O.downsample_box(I, s).astype(np.float32)
+    if lr_op == "f1":
+        T = synth.lr_op_f1(L)
+    else:
+        T = synth.lr_op_f2(L)
+    if C == 1:
+        T = T[..., :1]
+    elif C == 2:
+        T = T[..., :2]
+    elif C == 4:
+        T = np.concatenate([T, T[..., :1] * 0.5], axis=-1)
+    return I, np.ascontiguousarray(L.astype(np.float32)), np.ascontiguousarray(T.astype(np.float32))
+
+
+def _run_and_check(glu, I, L, T, s, k, mode, eps=1e-3, dtype=torch.float32, fused_too=True):
+    npd = np.float16 if dtype == torch.float16 else np.float32
+    I = I.astype(npd)
+    L = L.astype(npd)
+    T = T.astype(npd)
+    dI, dL, dT = dev(I), dev(L), dev(T)
+    th, err = glu.search(dI, dL, s, k, eps, mode, return_err=True)
+    out = glu.apply(th, dT, s, k)
+    code, alpha, e, That = host(th.code), host(th.alpha), host(err), host(out)
+    rep = check_search(I, L, s, k, eps, mode, code, alpha, err=e, T_low=T, T_hat=That, out_dtype=npd)
+    if fused_too:
+        out2, th2, err2 = glu.search_apply(dI, dL, dT, s, k, eps, mode, return_err=True)
+        # the fused pass gives bitwise the same Theta, E and T_hat as the two calls
+        assert np.array_equal(host(th2.code), code)
+        assert np.array_equal(host(th2.alpha).view(np.uint32), alpha.view(np.uint32))
+        assert np.array_equal(host(err2).view(np.uint32), e.view(np.uint32))
+        assert np.array_equal(host(out2), That)
+        out3, th3 = glu.search_apply(dI, dL, dT, s, k, eps, mode, store_theta=False)
+        assert th3 is None
+        assert np.array_equal(host(out3), That)
+    return rep
+
+
+@pytest.mark.parametrize("mode", ["exhaustive", "fast"])
+def test_plain_512_box4(mode):
+    """Plain GLU on a 512 x 512 Voronoi image, box x4 to 128 x 128, 3 x 3 window."""
+    glu = _glu()
+    log_case(test="plain_512_box4", mode=mode)
+    I, L, T = _inputs(512, 512, 4, seed=1, n_cells=64, n_dots=20, dot_px=(2, 4), down="box")
+    rep = _run_and_check(glu, I, L, T, 4, 3, mode)
+    print(rep)
+
+
+CASES = [
+    # H, W, s, k, C, mode, dtype
+    (37, 53, 4, 3, 3, "exhaustive", "f32"),
+    (64, 96, 8, 3, 1, "fast", "f32"),
+    (29, 31, 3, 3, 4, "exhaustive", "f32"),
+    (29, 31, 3, 3, 2, "fast", "f32"),
+    (50, 70, 2, 5, 3, "exhaustive", "f32"),
+    (72, 88, 4, 5, 3, "exhaustive", "f32"),
+    (72, 88, 8, 5, 3, "fast", "f32"),
+    (40, 40, 8, 1, 3, "exhaustive", "f32"),
+    (40, 40, 8, 1, 3, "fast", "f32"),
+    (41, 39, 4, 7, 3, "exhaustive", "f32"),
+    (41, 39, 4, 7, 3, "fast", "f32"),
+    (23, 17, 16, 3, 3, "exhaustive", "f32"),
+    (5, 7, 8, 3, 3, "exhaustive", "f32"),
+    (1, 1, 1, 3, 1, "exhaustive", "f32"),
+    (16, 24, 1, 3, 3, "exhaustive", "f32"),
+    (16, 24, 1, 3, 3, "fast", "f32"),
+    (130, 170, 16, 3, 3, "exhaustive", "f32"),
+    (200, 264, 8, 3, 3, "exhaustive", "f16"),
+    (200, 264, 8, 3, 3, "fast", "f16"),
+    (57, 61, 4, 3, 1, "exhaustive", "f16"),
+    (96, 100, 12, 3, 3, "exhaustive", "f32"),
+    (48, 48, 4, 9, 3, "exhaustive", "f32"),
+]
+
+
+@pytest.mark.parametrize("H,W,s,k,C,mode,dt", CASES)
+def test_shapes(H, W, s, k, C, mode, dt):
+    glu = _glu()
+    log_case(test="shapes", H=H, W=W, s=s, k=k, C=C, mode=mode, dt=dt)
+    I, L, T = _inputs(H, W, s, seed=H * 131 + W, n_cells=max(4, H * W // 400), n_dots=3, C=C)
+    dtype = torch.float16 if dt == "f16" else torch.float32
+    _run_and_check(glu, I, L, T, s, k, mode, dtype=dtype)
+
+
+@pytest.mark.parametrize("mode", ["exhaustive", "fast"])
+def test_eps_zero_well_separated(mode):
+    """eps = 0 (no regulariser) on a well-separated palette image."""
+    glu = _glu()
+    rng = np.random.default_rng(3)
+    pal = rng.uniform(0, 1, (6, 3))
+    lab = rng.integers(0, 6, (20, 28))
+    I = np.repeat(np.repeat(pal[lab], 4, 0), 4, 1)[:75, :106].astype(np.float32)
+    I = np.clip(I + rng.normal(0, 0.02, I.shape), 0, 1).astype(np.float32)
+    L = O.downsample_point(I, 4)
+    T = synth.lr_op_f1(L).astype(np.float32)
+    _run_and_check(glu, I, L, T, 4, 3, mode, eps=0.0)
+
+
+@pytest.mark.parametrize("mode", ["exhaustive", "fast"])
+def test_nearest_copy_exact_zero(mode):
+    """HR = s x s replicas of LR: E is exactly 0 and T_hat nearest-neighbour."""
+    glu = _glu()
+    rng = np.random.default_rng(7)
+    s = 8
+    L = rng.uniform(0, 1, (30, 41, 3)).astype(np.float32)
+    I = np.ascontiguousarray(np.repeat(np.repeat(L, s, 0), s, 1)[:235, :321])
+    T = rng.uniform(0, 1, (30, 41, 2)).astype(np.float32)
+    out, th, err = glu.search_apply(dev(I), dev(L), dev(T), s, 3, 1e-3, mode, return_err=True)
+    assert np.all(host(err) == 0.0)
+    nn = np.repeat(np.repeat(T, s, 0), s, 1)[:235, :321]
+    assert np.array_equal(host(out), nn)
+
+
+def test_constant_image():
+    glu = _glu()
+    I = np.broadcast_to(np.array([0.3, 0.6, 0.2], np.float32), (70, 90, 3)).copy()
+    L = O.downsample_point(I, 8)
+    T = np.full(L.shape[:2] + (1,), 0.7, np.float32)
+    for mode in ("exhaustive", "fast"):
+        out, th, err = glu.search_apply(dev(I), dev(L), dev(T), 8, 3, 1e-3, mode, return_err=True)
+        assert np.all(host(err) == 0.0)
+        assert np.all(host(out) == np.float32(0.7))
+
+
+def test_empty_image_is_a_no_op():
+    glu = _glu()
+    I = torch.empty((0, 16, 3), device="cuda")
+    L = torch.empty((0, 2, 3), device="cuda")
+    th = glu.search(I, L, 8, 3)
+    assert th.code.shape == (0, 16)
+
+
+def test_determinism_and_theta_expand():
+    glu = _glu()
+    I, L, T = _inputs(160, 200, 8, seed=9, n_cells=30, n_dots=8)
+    dI, dL = dev(I), dev(L)
+    th1, e1 = glu.search(dI, dL, 8, 3, return_err=True)
+    th2, e2 = glu.search(dI, dL, 8, 3, return_err=True)
+    assert torch.equal(th1.code, th2.code) and torch.equal(th1.alpha, th2.alpha) and torch.equal(e1, e2)
+    a, b = glu.theta_expand(th1, 8, 3)
+    from tests.parity import decode_codes
+
+    pix = np.arange(160 * 200)
+    ra, rb, ok = decode_codes(host(th1.code), 160, 200, 8, 3, pix)
+    assert ok.all()
+    assert np.array_equal(host(a).ravel(), ra) and np.array_equal(host(b).ravel(), rb)
+
+
+@pytest.mark.parametrize("mode", ["point", "box"])
+def test_downsample(mode):
+    glu = _glu()
+    I = synth.voronoi(67, 93, n_cells=10, n_dots=4, seed=5)
+    out = host(glu.downsample(dev(I), 8, mode))
+    if mode == "point":
+        assert np.array_equal(out, O.downsample_point(I, 8))
+    else:
+        np.testing.assert_allclose(out, O.downsample_box(I, 8), atol=1e-6)
+
+
+def test_padded_rows_and_views():
+    """Row strides larger than W*C (views into wider buffers) give the same result."""
+    glu = _glu()
+    I, L, T = _inputs(64, 80, 4, seed=21, n_cells=12, n_dots=4)
+    big = np.zeros((64, 84, 3), np.float32)
+    big[:, :80] = I
+    dI = dev(big)[:, :80]
+    th, e = glu.search(dI, dev(L), 4, 3, return_err=True)
+    th0, e0 = glu.search(dev(I), dev(L), 4, 3, return_err=True)
+    assert torch.equal(th.code, th0.code) and torch.equal(th.alpha, th0.alpha)
+
+
+@pytest.mark.parametrize("mode", ["exhaustive", "fast"])
+def test_full_4k_x8_sampled(mode):
+    """The 3840 x 2160 x8 workload, in the launch configuration the benchmark
+    times (fused search + apply), checked on sampled pixels: 20000 random
+    pixels plus every pixel of the first and last tile rows and columns."""
+    glu = _glu()
+    log_case(test="full_4k_x8_sampled", mode=mode)
+    H, W, s = 2160, 3840, 8
+    I = synth.voronoi(H, W, n_cells=1000, n_dots=400, dot_px=(1, 3), seed=3)
+    L = O.downsample_point(I, s)
+    T = synth.lr_op_f1(L).astype(np.float32)
+    out, th, err = glu.search_apply(dev(I), dev(L), dev(T), s, 3, 1e-3, mode, return_err=True)
+    rng = np.random.default_rng(0)
+    pix = [rng.choice(H * W, 20000, replace=False)]
+    ys, xs = np.mgrid[0:H, 0:W]
+    edge = (ys < 16) | (ys >= H - 16) | (xs < 64) | (xs >= W - 64)
+    pix.append(np.flatnonzero(edge.ravel())[::7])
+    pix = np.unique(np.concatenate(pix))
+    rep = check_search(I, L, s, 3, 1e-3, mode, host(th.code), host(th.alpha), err=host(err), pixels=pix,
+                       T_low=T, T_hat=host(out))
+    print(rep)
