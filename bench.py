@@ -44,7 +44,7 @@ FLOPS_PER_PX = {"exhaustive": 27 + 5 + 36 * 17, "fast": 9 * 9 + 9 * 21}
 # Algorithmic HBM bytes per HR pixel (C = 3, float32): search reads I (12)
 # and writes Theta (6); apply reads Theta (6) and writes T_hat (12); fused
 # reads I and writes Theta and T_hat.
-BYTES_PER_PX = {"search": 18, "apply": 18, "step": 36, "fused": 30}
+BYTES_PER_PX = {"search": 18, "apply": 18, "step": 36, "fused": 30, "bwd": 22}
 
 
 def _parse():
@@ -181,6 +181,26 @@ def main():
     else:
         kern[args.mode] = dict(search_us=float("nan"))
 
+    bwd = None
+    if args.only == "all":
+        # backward of the apply step on the same frames (Theta from the search)
+        G = torch.randn((H, W, 3), dtype=torch.float32, device=dev, generator=torch.Generator(dev).manual_seed(5))
+        ws = torch.empty(glu.apply_backward_workspace(H, W, 3, S, K) // 4 + 1, dtype=torch.float32, device=dev)
+        gT = torch.empty((H // S, W // S, 3), dtype=torch.float32, device=dev)
+        ga = torch.empty((H, W), dtype=torch.float32, device=dev)
+
+        def backward(i, mode):
+            st = sets[i % len(sets)]
+            glu.apply_backward(st["th"], st["T"], G, S, K, workspace=ws, out_T_low=gT, out_alpha=ga)
+
+        bwd_ms = timed(backward, args.mode, args.steps, 3)
+        bwd = {
+            "us": round(1e3 * bwd_ms, 2),
+            "Mpx_s": round(n_px / (bwd_ms * 1e-3) / 1e6, 1),
+            "bytes_per_px": BYTES_PER_PX["bwd"],
+            "hbm_frac": round(BYTES_PER_PX["bwd"] * n_px / (bwd_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        }
+
     ks = kern[args.mode]
     roof = None
     if args.only == "all":
@@ -230,6 +250,7 @@ def main():
         },
         "roofline": roof,
         "kernels_us": {m: {k2: round(v, 2) for k2, v in d.items()} for m, d in kern.items()},
+        "bwd": bwd,
         "cpu_baseline": cpu,
         "wall_s_timed_region": round(wall, 4),
     }

@@ -180,22 +180,30 @@ glu_status glu_search_apply(const glu_image* I, const glu_image* I_low, const gl
                             void* stream);
 
 /* ---------------------------------------------------------------------------
- * glu_apply_backward - gradients of Eq. 1 with the indices (a, b) held fixed:
+ * glu_apply_backward - gradients of Eq. 1 (Sec. 3.1) with the indices (a, b)
+ * held fixed (the indices are piecewise constant in the inputs):
  *
  *   grad_alpha_p = sum_c G_p,c (T_low[a_p],c - T_low[b_p],c)
  *   grad_T_low_q = sum_{p: a_p = q} alpha_p G_p + sum_{p: b_p = q} (1 - alpha_p) G_p
  *
+ *   theta       H x W, as written by glu_search (s, k in p must match).
+ *   T_low       ceil(H/s) x ceil(W/s) x C, 1 <= C <= 4, GLU_F32 or GLU_F16.
  *   grad_T_hat  G, H x W x C, GLU_F32.
  *   grad_T_low  nullable output, ceil(H/s) x ceil(W/s) x C, GLU_F32 (written,
  *               not accumulated).
  *   grad_alpha  nullable output, float, theta layout.
+ *   workspace   device scratch of glu_apply_backward_workspace() bytes,
+ *               needed only when grad_T_low is requested (contents on entry
+ *               ignored; caller-owned).
  * grad_T_low is a gather over the inverted index map: each LR cell sums the
- * contributions of the HR pixels whose window can reach it, in a fixed
- * order, without atomics.
+ * contributions of the HR pixels whose window can reach it in a fixed order
+ * (per source block, then per window offset), without atomics, so the
+ * result is bitwise reproducible.
  * ------------------------------------------------------------------------- */
+size_t glu_apply_backward_workspace(int32_t H, int32_t W, int32_t C, const glu_params* p);
 glu_status glu_apply_backward(const glu_theta* theta, const glu_image* T_low, const glu_params* p,
                               const glu_image* grad_T_hat, glu_image* grad_T_low,
-                              float* grad_alpha, void* stream);
+                              float* grad_alpha, void* workspace, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
  * glu_downsample - initial LR guide (not on the timed path).

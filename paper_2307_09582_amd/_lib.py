@@ -115,9 +115,20 @@ _SIGS = {
         C.c_int,
         [P(glu_image), P(glu_image), P(glu_image), P(glu_params), P(glu_theta), C.c_void_p, P(glu_image), C.c_void_p],
     ),
+    "glu_apply_backward_workspace": (C.c_size_t, [C.c_int32, C.c_int32, C.c_int32, P(glu_params)]),
     "glu_apply_backward": (
         C.c_int,
-        [P(glu_theta), P(glu_image), P(glu_params), P(glu_image), P(glu_image), C.c_void_p, C.c_void_p],
+        [
+            P(glu_theta),
+            P(glu_image),
+            P(glu_params),
+            P(glu_image),
+            P(glu_image),
+            C.c_void_p,
+            C.c_void_p,
+            C.c_size_t,
+            C.c_void_p,
+        ],
     ),
     "glu_downsample": (C.c_int, [P(glu_image), P(glu_image), C.c_int32, C.c_int32, C.c_void_p]),
     "glu_theta_expand": (C.c_int, [P(glu_theta), P(glu_params), C.c_void_p, C.c_void_p, C.c_void_p]),

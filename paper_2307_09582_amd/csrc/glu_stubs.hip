@@ -5,11 +5,6 @@ using namespace glu;
 
 extern "C" {
 
-glu_status glu_apply_backward(const glu_theta*, const glu_image*, const glu_params*, const glu_image*, glu_image*,
-                              float*, void*) {
-  return fail(GLU_ERR_UNSUPPORTED, "glu_apply_backward not built");
-}
-
 size_t glu_joint_downsample_workspace(int32_t, int32_t, const glu_params*) { return 0; }
 
 glu_status glu_joint_downsample(const glu_image*, glu_image*, const glu_params*, float, int32_t, glu_theta*, float*,

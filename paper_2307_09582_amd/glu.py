@@ -179,13 +179,31 @@ def theta_expand(theta: Theta, s: int, k: int = 3):
     return a, b
 
 
-def apply_backward(theta: Theta, T_low, grad_T_hat, s, k=3, need_T_low=True, need_alpha=True):
+def apply_backward_workspace(H: int, W: int, C: int, s: int, k: int = 3) -> int:
+    lib = L.load()
+    p = _params(s, k, EPS)
+    return int(lib.glu_apply_backward_workspace(int(H), int(W), int(C), C.byref(p)))
+
+
+def apply_backward(theta: Theta, T_low, grad_T_hat, s, k=3, need_T_low=True, need_alpha=True, workspace=None,
+                   out_T_low=None, out_alpha=None):
     """Gradients of Eq. 1 (indices fixed): returns (grad_T_low or None, grad_alpha or None)."""
     H, W = theta.shape
-    gT = torch.empty(T_low.shape, dtype=torch.float32, device=T_low.device) if need_T_low else None
-    ga = torch.empty((H, W), dtype=torch.float32, device=T_low.device) if need_alpha else None
+    Cn = T_low.shape[2]
+    gT = None
+    if need_T_low:
+        gT = out_T_low if out_T_low is not None else torch.empty(
+            T_low.shape, dtype=torch.float32, device=T_low.device)
+    ga = None
+    if need_alpha:
+        ga = out_alpha if out_alpha is not None else torch.empty((H, W), dtype=torch.float32, device=T_low.device)
     p = _params(s, k, EPS)
     lib = L.load()
+    ws_bytes = 0
+    if need_T_low:
+        ws_bytes = int(lib.glu_apply_backward_workspace(H, W, Cn, C.byref(p)))
+        if workspace is None or workspace.numel() * workspace.element_size() < ws_bytes:
+            workspace = torch.empty(max(1, ws_bytes // 4), dtype=torch.float32, device=T_low.device)
     L.check(
         lib.glu_apply_backward(
             C.byref(_theta(theta)),
@@ -194,6 +212,8 @@ def apply_backward(theta: Theta, T_low, grad_T_hat, s, k=3, need_T_low=True, nee
             C.byref(_img(grad_T_hat, "grad_T_hat")),
             C.byref(_img(gT, "grad_T_low")) if gT is not None else None,
             C.c_void_p(ga.data_ptr() if ga is not None and ga.numel() else None),
+            C.c_void_p(workspace.data_ptr() if workspace is not None else None),
+            ws_bytes,
             _stream(),
         )
     )

@@ -1,0 +1,173 @@
+"""GPU parity of glu_apply_backward and the GluApply autograd function."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import synth
+from tests.gpu_util import dev, host, log_case, need_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _glu():
+    need_gpu()
+    import paper_2307_09582_amd as glu
+
+    return glu
+
+
+def random_theta(H, W, s, k, seed):
+    """Random valid Theta: both endpoints inside the truncated window."""
+    rng = np.random.default_rng(seed)
+    h, w = -(-H // s), -(-W // s)
+    r = k // 2
+    ys, xs = np.mgrid[0:H, 0:W]
+    qy, qx = ys // s, xs // s
+
+    def pick():
+        cy = np.clip(qy + rng.integers(-r, r + 1, (H, W)), 0, h - 1)
+        cx = np.clip(qx + rng.integers(-r, r + 1, (H, W)), 0, w - 1)
+        return (cy - qy + r) * k + (cx - qx + r), cy * w + cx
+
+    oa, a = pick()
+    ob, b = pick()
+    code = (oa * k * k + ob).astype(np.uint16)
+    alpha = rng.uniform(0, 1, (H, W)).astype(np.float32)
+    alpha[rng.uniform(size=(H, W)) < 0.1] = 1.0
+    same = rng.uniform(size=(H, W)) < 0.1
+    code[same] = (oa[same] * k * k + oa[same]).astype(np.uint16)
+    b = np.where(same, a, b)
+    return code, alpha, a, b
+
+
+def _check(glu, H, W, s, k, C, seed, t_dtype=torch.float32):
+    log_case(test="backward", H=H, W=W, s=s, k=k, C=C, seed=seed)
+    code, alpha, a, b = random_theta(H, W, s, k, seed)
+    rng = np.random.default_rng(seed + 1)
+    h, w = -(-H // s), -(-W // s)
+    T = rng.uniform(0, 1, (h, w, C)).astype(np.float32)
+    if t_dtype == torch.float16:
+        T = T.astype(np.float16)
+    G = rng.normal(0, 1, (H, W, C)).astype(np.float32)
+    th = glu.Theta(dev(code.view(np.int16)), dev(alpha))
+    gT, ga = glu.apply_backward(th, dev(T), dev(G), s, k)
+    gT, ga = host(gT), host(ga)
+    da_ref, dT_ref = O.apply_backward(a.ravel(), b.ravel(), alpha.ravel(), T.astype(np.float64), G.astype(np.float64))
+    da_ref = da_ref.reshape(H, W)
+    assert np.all(np.abs(ga - da_ref) <= 1e-5 * (1 + np.abs(da_ref))), float(np.abs(ga - da_ref).max())
+    # per-cell L1 mass of the summed contributions bounds the rounding of the sum
+    mass = np.zeros((h * w, C))
+    Gf = np.abs(G.reshape(-1, C).astype(np.float64))
+    np.add.at(mass, a.ravel(), alpha.ravel()[:, None] * Gf)
+    np.add.at(mass, b.ravel(), (1 - alpha.ravel())[:, None] * Gf)
+    err = np.abs(gT.reshape(-1, C) - dT_ref.reshape(-1, C))
+    assert np.all(err <= 1e-5 * mass + 1e-12), float((err / (mass + 1e-30)).max())
+    # bitwise determinism
+    gT2, ga2 = glu.apply_backward(th, dev(T), dev(G), s, k)
+    assert np.array_equal(host(gT2), gT) and np.array_equal(host(ga2), ga)
+    # only one of the two outputs
+    gT3, ga3 = glu.apply_backward(th, dev(T), dev(G), s, k, need_alpha=False)
+    assert ga3 is None and np.array_equal(host(gT3), gT)
+    gT4, ga4 = glu.apply_backward(th, dev(T), dev(G), s, k, need_T_low=False)
+    assert gT4 is None and np.array_equal(host(ga4), ga)
+
+
+@pytest.mark.parametrize(
+    "H,W,s,k,C",
+    [
+        (256, 320, 8, 3, 3),
+        (100, 77, 3, 3, 4),
+        (64, 72, 4, 5, 1),
+        (130, 170, 16, 3, 2),
+        (33, 29, 2, 7, 3),
+        (7, 5, 8, 3, 1),
+        (512, 512, 8, 3, 3),
+        (96, 96, 32, 3, 3),
+    ],
+)
+def test_backward_parity(H, W, s, k, C):
+    _check(_glu(), H, W, s, k, C, seed=H + 7 * W + s)
+
+
+def test_backward_half_T_low():
+    _check(_glu(), 120, 136, 8, 3, 3, seed=5, t_dtype=torch.float16)
+
+
+def test_backward_fd_on_crops():
+    """FP64 central finite differences of the oracle loss on 64 x 64 crops,
+    against the GPU gradients of the same quadratic loss."""
+    glu = _glu()
+    H = W = 1024
+    s, k = 8, 3
+    I = synth.voronoi(H, W, n_cells=150, n_dots=40, dot_px=(1, 3), seed=5)
+    L = O.downsample_point(I, s)
+    T = synth.lr_op_f1(L).astype(np.float32)
+    th = glu.search(dev(I), dev(L), s, k)
+    code, alpha = host(th.code), host(th.alpha)
+    from tests.parity import decode_codes
+
+    a, b, ok = decode_codes(code, H, W, s, k, np.arange(H * W))
+    assert ok.all()
+    rng = np.random.default_rng(5)
+    target = (synth.lr_op_f1(I) + rng.normal(0, 0.01, (H, W, 3))).astype(np.float32)
+    for ci in range(4):
+        y0 = int(rng.integers(0, (H - 64) // s)) * s
+        x0 = int(rng.integers(0, (W - 64) // s)) * s
+        mask = np.zeros((H, W, 1), np.float32)
+        mask[y0 : y0 + 64, x0 : x0 + 64] = 1.0
+        out = host(glu.apply(th, dev(T), s, k))
+        G = (2.0 * (out - target) * mask).astype(np.float32)
+        gT, ga = glu.apply_backward(th, dev(T), dev(G), s, k)
+        gT, ga = host(gT), host(ga)
+        pix = np.flatnonzero(mask[..., 0].ravel())
+        tgt = target.reshape(-1, 3)[pix].astype(np.float64)
+
+        def loss(Tl, al):
+            o = O.apply(a.ravel()[pix], b.ravel()[pix], al[pix], Tl)
+            return float(((o - tgt) ** 2).sum())
+
+        al64 = alpha.ravel().astype(np.float64)
+        T64 = T.astype(np.float64)
+        eps = 1e-6
+        # LR entries the crop touches
+        cells = np.unique(np.concatenate([a.ravel()[pix], b.ravel()[pix]]))
+        for q in rng.choice(cells, 6, replace=False):
+            for c in range(3):
+                Tp, Tm = T64.copy(), T64.copy()
+                Tp.reshape(-1, 3)[q, c] += eps
+                Tm.reshape(-1, 3)[q, c] -= eps
+                fd = (loss(Tp, al64) - loss(Tm, al64)) / (2 * eps)
+                g = gT.reshape(-1, 3)[q, c]
+                assert abs(g - fd) <= 1e-5 * (1 + abs(fd)) + 1e-4, (q, c, g, fd)
+        for p in rng.choice(pix, 8, replace=False):
+            ap, am = al64.copy(), al64.copy()
+            ap[p] += eps
+            am[p] -= eps
+            fd = (loss(T64, ap) - loss(T64, am)) / (2 * eps)
+            assert abs(ga.ravel()[p] - fd) <= 1e-5 * (1 + abs(fd)) + 1e-5, (p, ga.ravel()[p], fd)
+
+
+def test_autograd_function_matches_torch_reference():
+    """GluApply inside a loss: gradients equal a float64 CPU autograd reference
+    built from index_select."""
+    glu = _glu()
+    H, W, s, k = 96, 128, 8, 3
+    code, alpha, a, b = random_theta(H, W, s, k, 17)
+    rng = np.random.default_rng(17)
+    T = rng.uniform(0, 1, (H // s, W // s, 3)).astype(np.float32)
+    target = rng.uniform(0, 1, (H, W, 3)).astype(np.float32)
+    al_t = dev(alpha).requires_grad_(True)
+    T_t = dev(T).requires_grad_(True)
+    out = glu.glu_apply_autograd(al_t, T_t, dev(code.view(np.int16)), s, k)
+    loss = ((out - dev(target)) ** 2).mean()
+    loss.backward()
+    # reference in float64 on the CPU
+    Tr = torch.tensor(T.reshape(-1, 3), dtype=torch.float64, requires_grad=True)
+    ar = torch.tensor(alpha.ravel(), dtype=torch.float64, requires_grad=True)
+    o = ar[:, None] * Tr.index_select(0, torch.tensor(a.ravel())) + (1 - ar[:, None]) * Tr.index_select(
+        0, torch.tensor(b.ravel()))
+    lr = ((o - torch.tensor(target.reshape(-1, 3), dtype=torch.float64)) ** 2).mean()
+    lr.backward()
+    np.testing.assert_allclose(host(al_t.grad).ravel(), ar.grad.numpy(), rtol=1e-4, atol=1e-9)
+    np.testing.assert_allclose(host(T_t.grad).reshape(-1, 3), Tr.grad.numpy(), rtol=1e-4, atol=1e-9)
