@@ -12,6 +12,7 @@ from .glu import (  # noqa: F401
     Theta,
     apply,
     apply_backward,
+    apply_backward_workspace,
     downsample,
     empty_theta,
     glu_apply_autograd,

@@ -108,6 +108,17 @@ TileChoice choose_tile(int s, int k, int mode, bool fused, bool table, int varia
   return tc;
 }
 
+TileChoice choose_apply_tile(int s, int k) {
+  TileChoice tc;
+  tc.P = (s % 4 == 0) ? 4 : 1;
+  tc.tqx = std::max(1, 64 / s);
+  const int rows = std::max(1, kApplyStrips * kThreads * tc.P / (tc.tqx * s));
+  tc.tqy = std::max(1, rows / s);
+  const int r = k / 2;
+  while (16 * (tc.tqy + 2 * r) * (tc.tqx + 2 * r) > kLdsBudget && tc.tqy > 1) tc.tqy = (tc.tqy + 1) / 2;
+  return tc;
+}
+
 void fill_tiles(ImgDesc& d, const TileChoice& tc) {
   d.tqy = tc.tqy;
   d.tqx = tc.tqx;
@@ -137,7 +148,7 @@ __global__ __launch_bounds__(kThreads) void k_apply(const ImgDesc d) {
   extern __shared__ float4 smem[];
   const int tile = blockIdx.x;
   const int ty = tile / d.tiles_x, tx = tile - ty * d.tiles_x;
-  apply_tile<KW, P, T>(d, ty, tx, smem);
+  apply_tile<KW, P, T, kApplyStrips>(d, ty, tx, smem);
 }
 
 typedef void (*SearchKernel)(const ImgDesc, float);
@@ -371,7 +382,7 @@ glu_status glu_apply(const glu_theta* theta, const glu_image* T_low, const glu_p
   d.k = p->k;
   d.C = T_low->channels;
   d.dtype = T_low->dtype;
-  TileChoice tc = choose_tile(p->s, p->k, MODE_FAST, false, false, 0);
+  TileChoice tc = choose_apply_tile(p->s, p->k);
   fill_tiles(d, tc);
   d.vec = vec_flags(d, tc.P, dtype_size(T_low->dtype));
   const int r = p->k / 2;

@@ -36,6 +36,10 @@ __device__ __forceinline__ __half from_f<__half>(float v) { return __float2half_
 
 __device__ __forceinline__ float clamp01(float x) { return __builtin_amdgcn_fmed3f(x, 0.0f, 1.0f); }
 
+// Clang vector types for the non-temporal load/store builtins.
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
 // ---------------------------------------------------------------------------
 // HR strip loads and stores (P consecutive pixels of one row)
 // ---------------------------------------------------------------------------
@@ -522,7 +526,10 @@ __device__ __forceinline__ void search_tile(const ImgDesc& d, int ty, int tx, fl
 // ---------------------------------------------------------------------------
 // One tile of apply (Eq. 1)
 // ---------------------------------------------------------------------------
-template <int KW, int P, typename T>
+// Apply is a pure stream (6 bytes of Theta in, 4C bytes out per pixel), so a
+// thread owns NS strips and issues all their Theta loads before the LDS
+// staging barrier; the T_low window of the tile is staged once.
+template <int KW, int P, typename T, int NS>
 __device__ __forceinline__ void apply_tile(const ImgDesc& d, int ty, int tx, float4* smem) {
   const int kw = KW > 0 ? KW : d.k;
   const int R = kw / 2;
@@ -532,62 +539,90 @@ __device__ __forceinline__ void apply_tile(const ImgDesc& d, int ty, int tx, flo
   const int qy0 = ty * tqy, qx0 = tx * tqx;
   const int ly = tqy + 2 * R, lx = tqx + 2 * R;
   float4* sT = smem;
-  stage_lr<T>(d, qy0, qx0, R, ly, lx, nullptr, sT);
-  __syncthreads();
-
   const int rows = tqy * s, cols = tqx * s;
   const int spr = cols / P;
   const int nstrips = rows * spr;
   const bool interior = ((qy0 + tqy) * s <= d.H) && ((qx0 + tqx) * s <= d.W);
   const bool vecTh = (d.vec & VEC_THETA) != 0, vecT = (d.vec & VEC_T) != 0;
   const int maxcode = K2 * K2 - 1;
-  for (int t = threadIdx.x; t < nstrips; t += kThreads) {
-    const int ry = t / spr;
-    const int rx = (t - ry * spr) * P;
-    const int y = qy0 * s + ry, x = qx0 * s + rx;
-    if (y >= d.H || x >= d.W) continue;
-    const int cy = ry / s, cx = rx / s;
-    const bool full = interior || (x + P <= d.W);
-    const int64_t to = (int64_t)y * d.th_stride + x;
-    int code[P];
-    float al[P];
-    bool done = false;
-    if constexpr (P == 4) {
-      if (vecTh && full) {
-        const uint2 c = *reinterpret_cast<const uint2*>(d.code + to);
-        const float4 a4 = *reinterpret_cast<const float4*>(d.alpha + to);
-        code[0] = c.x & 0xffff;
-        code[1] = c.x >> 16;
-        code[2] = c.y & 0xffff;
-        code[3] = c.y >> 16;
-        al[0] = a4.x;
-        al[1] = a4.y;
-        al[2] = a4.z;
-        al[3] = a4.w;
-        done = true;
+
+  for (int base = 0; base < nstrips; base += NS * kThreads) {
+    // strip coordinates: t = base + tid + n * kThreads, walked without divisions
+    int ry[NS], rx[NS];
+    {
+      const int t0 = base + threadIdx.x;
+      const int ry0 = t0 / spr;
+      const int dr = kThreads / spr, dc = kThreads - dr * spr;
+      int r0 = ry0, c0 = t0 - ry0 * spr;
+#pragma unroll
+      for (int n = 0; n < NS; ++n) {
+        ry[n] = r0;
+        rx[n] = c0 * P;
+        r0 += dr;
+        c0 += dc;
+        if (c0 >= spr) {
+          c0 -= spr;
+          r0 += 1;
+        }
       }
     }
-    if (!done) {
+    int code[NS][P];
+    float al[NS][P];
+#pragma unroll
+    for (int n = 0; n < NS; ++n) {
+      const int y = qy0 * s + ry[n], x = qx0 * s + rx[n];
+      const bool live = (base + threadIdx.x + n * kThreads < nstrips) && y < d.H && x < d.W;
+      const bool full = interior || (x + P <= d.W);
+      const int64_t to = (int64_t)y * d.th_stride + x;
+      bool done = false;
+      if constexpr (P == 4) {
+        if (live && vecTh && full) {
+          const u32x2 c = __builtin_nontemporal_load(reinterpret_cast<const u32x2*>(d.code + to));
+          const f32x4 a4 = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(d.alpha + to));
+          code[n][0] = c.x & 0xffff;
+          code[n][1] = c.x >> 16;
+          code[n][2] = c.y & 0xffff;
+          code[n][3] = c.y >> 16;
+          al[n][0] = a4.x;
+          al[n][1] = a4.y;
+          al[n][2] = a4.z;
+          al[n][3] = a4.w;
+          done = true;
+        }
+      }
+      if (!done) {
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+          const bool ok = live && (full || (x + q < d.W));
+          code[n][q] = ok ? d.code[to + q] : 0;
+          al[n][q] = ok ? d.alpha[to + q] : 0.0f;
+        }
+      }
+    }
+    if (base == 0) {
+      stage_lr<T>(d, qy0, qx0, R, ly, lx, nullptr, sT);
+      __syncthreads();
+    }
+#pragma unroll
+    for (int n = 0; n < NS; ++n) {
+      const int y = qy0 * s + ry[n], x = qx0 * s + rx[n];
+      if (!((base + threadIdx.x + n * kThreads < nstrips) && y < d.H && x < d.W)) continue;
+      const bool full = interior || (x + P <= d.W);
+      const int cy = ry[n] / s, cx = rx[n] / s;
+      float o[P][4];
 #pragma unroll
       for (int q = 0; q < P; ++q) {
-        const bool ok = full || (x + q < d.W);
-        code[q] = ok ? d.code[to + q] : 0;
-        al[q] = ok ? d.alpha[to + q] : 0.0f;
+        const int cd = min(code[n][q], maxcode);
+        const int oa = cd / K2, ob = cd - oa * K2;
+        const float4 Ta = sT[(cy + oa / kw) * lx + cx + oa % kw];
+        const float4 Tb = sT[(cy + ob / kw) * lx + cx + ob % kw];
+        o[q][0] = fmaf(al[n][q], Ta.x - Tb.x, Tb.x);
+        o[q][1] = fmaf(al[n][q], Ta.y - Tb.y, Tb.y);
+        o[q][2] = fmaf(al[n][q], Ta.z - Tb.z, Tb.z);
+        o[q][3] = fmaf(al[n][q], Ta.w - Tb.w, Tb.w);
       }
+      store_out<T, P>(static_cast<T*>(d.That) + (int64_t)y * d.That_stride, x, d.W, d.C, vecT, full, o);
     }
-    float o[P][4];
-#pragma unroll
-    for (int q = 0; q < P; ++q) {
-      const int cd = min(code[q], maxcode);
-      const int oa = cd / K2, ob = cd - oa * K2;
-      const float4 Ta = sT[(cy + oa / kw) * lx + cx + oa % kw];
-      const float4 Tb = sT[(cy + ob / kw) * lx + cx + ob % kw];
-      o[q][0] = fmaf(al[q], Ta.x - Tb.x, Tb.x);
-      o[q][1] = fmaf(al[q], Ta.y - Tb.y, Tb.y);
-      o[q][2] = fmaf(al[q], Ta.z - Tb.z, Tb.z);
-      o[q][3] = fmaf(al[q], Ta.w - Tb.w, Tb.w);
-    }
-    store_out<T, P>(static_cast<T*>(d.That) + (int64_t)y * d.That_stride, x, d.W, d.C, vecT, full, o);
   }
 }
 

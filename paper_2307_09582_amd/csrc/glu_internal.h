@@ -12,6 +12,7 @@ namespace glu {
 constexpr int kThreads = 256;       // threads per workgroup (4 wave64)
 constexpr int kMaxK = 15;           // largest window (code fits uint16)
 constexpr int kLdsBudget = 60 * 1024;  // dynamic LDS per workgroup we allow
+constexpr int kApplyStrips = 4;     // strips per thread in the apply kernel
 
 // Alignment flags of one launch (all pixels of a launch share them).
 enum : uint32_t {
