@@ -197,6 +197,37 @@ __device__ __forceinline__ float pair_err2(float dx, float dy, float dz, float a
   return fmaf(rz, rz, fmaf(ry, ry, rx * rx));
 }
 
+// Window accessors: win(o) is the LR guide colour of window offset o
+// (o = (dy + r) * k + (dx + r)) with .w = 1 for a cell inside the LR image
+// and .w = 0 outside.
+//   LdsWin     - the tile's staged copy in LDS (window top-left at p, row
+//                pitch lx);
+//   GlobalWin  - straight from the LR guide in global memory, bypassing the
+//                vector L1 cache so that colours another thread of the same
+//                workgroup just rewrote are seen (joint downsampling).
+template <int KW>
+struct LdsWin {
+  const float4* __restrict__ p;
+  int lx;
+  int kw_rt;
+  __device__ __forceinline__ float4 operator()(int o) const {
+    const int kw = KW > 0 ? KW : kw_rt;
+    return p[(o / kw) * lx + (o % kw)];
+  }
+};
+
+struct GlobalWin {
+  const float* L;
+  int64_t Ls;
+  int qy, qx, h, w, kw, r;
+  __device__ __forceinline__ float4 operator()(int o) const {
+    const int cy = qy + o / kw - r, cx = qx + o % kw - r;
+    if (cy < 0 || cy >= h || cx < 0 || cx >= w) return make_float4(0.f, 0.f, 0.f, 0.f);
+    const volatile float* q = L + (int64_t)cy * Ls + (int64_t)cx * 3;
+    return make_float4(q[0], q[1], q[2], 1.0f);
+  }
+};
+
 __device__ __forceinline__ void pair_from_index(int p, int& i, int& j) {
   int jj = (int)((1.0f + sqrtf(1.0f + 8.0f * (float)p)) * 0.5f);
   while (jj * (jj - 1) / 2 > p) --jj;
@@ -216,8 +247,8 @@ __device__ __forceinline__ void pair_from_index(int p, int& i, int& j) {
 // most |I_p - L_j| (alpha >= 0 moves the point along the segment towards
 // the pixel), so only (0, 0) is evaluated.  Border windows evaluate every
 // valid candidate.
-template <int KW, int P, bool BORDER, bool TABLE>
-__device__ __forceinline__ void exh_strip(const float (&ip)[P][3], const float4* __restrict__ win, int lx,
+template <int KW, int P, bool BORDER, bool TABLE, typename Win>
+__device__ __forceinline__ void exh_strip(const float (&ip)[P][3], const Win& win,
                                           const float4* __restrict__ tab, float eps, int kw_rt,
                                           float (&best)[P], int (&code)[P]) {
   constexpr int kUnrollJ = KW == 3 ? 9 : 1;
@@ -230,7 +261,7 @@ __device__ __forceinline__ void exh_strip(const float (&ip)[P][3], const float4*
     code[q] = 0;
   }
   if (!BORDER) {
-    const float4 L0 = win[0];
+    const float4 L0 = win(0);
 #pragma unroll
     for (int q = 0; q < P; ++q) {
       const float dx = ip[q][0] - L0.x, dy = ip[q][1] - L0.y, dz = ip[q][2] - L0.z;
@@ -239,8 +270,7 @@ __device__ __forceinline__ void exh_strip(const float (&ip)[P][3], const float4*
   }
 #pragma unroll kUnrollJ
   for (int j = (BORDER ? 0 : 1); j < K2; ++j) {
-    const int jy = j / kw, jx = j - jy * kw;
-    const float4 Lj = win[jy * lx + jx];
+    const float4 Lj = win(j);
     if (BORDER && Lj.w == 0.0f) continue;
     float d[P][3];
 #pragma unroll
@@ -255,8 +285,7 @@ __device__ __forceinline__ void exh_strip(const float (&ip)[P][3], const float4*
       if (TABLE) {
         t = tab[pair_index(i, j)];
       } else {
-        const int iy = i / kw, ix = i - iy * kw;
-        const float4 Li = win[iy * lx + ix];
+        const float4 Li = win(i);
         if (BORDER && Li.w == 0.0f) continue;
         t = pair_consts(Li, Lj, eps);
       }
@@ -285,19 +314,19 @@ __device__ __forceinline__ void exh_strip(const float (&ip)[P][3], const float4*
 
 // Weight of the winning exhaustive pair, recomputed with the same arithmetic
 // the loop used.
-template <int KW, bool TABLE>
-__device__ __forceinline__ float exh_alpha(const float (&ip)[3], const float4* __restrict__ win, int lx,
+template <int KW, bool TABLE, typename Win>
+__device__ __forceinline__ float exh_alpha(const float (&ip)[3], const Win& win,
                                            const float4* __restrict__ tab, float eps, int kw_rt, int code) {
   const int kw = KW > 0 ? KW : kw_rt;
   const int K2 = kw * kw;
   const int oi = code / K2, oj = code - oi * K2;
   if (oi == oj) return 1.0f;
-  const float4 Lj = win[(oj / kw) * lx + (oj % kw)];
+  const float4 Lj = win(oj);
   float4 t;
   if (TABLE) {
     t = tab[pair_index(oi, oj)];
   } else {
-    const float4 Li = win[(oi / kw) * lx + (oi % kw)];
+    const float4 Li = win(oi);
     t = pair_consts(Li, Lj, eps);
   }
   if (t.w == 0.0f) return 1.0f;
@@ -310,8 +339,8 @@ __device__ __forceinline__ float exh_alpha(const float (&ip)[3], const float4* _
 // a = first window cell of least colour distance; then every b of the window
 // (b = a included, weight 1) with w_b = |I-L_b| / (|I-L_a| + |I-L_b| + eps),
 // keeping the first b of least error.
-template <int KW, int P, bool BORDER>
-__device__ __forceinline__ void fast_strip(const float (&ip)[P][3], const float4* __restrict__ win, int lx,
+template <int KW, int P, bool BORDER, typename Win>
+__device__ __forceinline__ void fast_strip(const float (&ip)[P][3], const Win& win,
                                            float eps, int kw_rt, float (&best)[P], int (&code)[P],
                                            float (&alpha)[P]) {
   constexpr int kUnrollJ = KW == 3 ? 9 : 1;
@@ -328,7 +357,7 @@ __device__ __forceinline__ void fast_strip(const float (&ip)[P][3], const float4
   }
 #pragma unroll kUnrollJ
   for (int j = 0; j < K2; ++j) {
-    const float4 Lj = win[(j / kw) * lx + (j % kw)];
+    const float4 Lj = win(j);
     if (BORDER && Lj.w == 0.0f) continue;
 #pragma unroll
     for (int q = 0; q < P; ++q) {
@@ -343,7 +372,7 @@ __device__ __forceinline__ void fast_strip(const float (&ip)[P][3], const float4
   float La[P][3], sa[P], omb[P];
 #pragma unroll
   for (int q = 0; q < P; ++q) {
-    const float4 A = win[(ia[q] / kw) * lx + (ia[q] % kw)];
+    const float4 A = win(ia[q]);
     La[q][0] = A.x;
     La[q][1] = A.y;
     La[q][2] = A.z;
@@ -354,7 +383,7 @@ __device__ __forceinline__ void fast_strip(const float (&ip)[P][3], const float4
   }
 #pragma unroll kUnrollJ
   for (int b = 0; b < K2; ++b) {
-    const float4 Lb = win[(b / kw) * lx + (b % kw)];
+    const float4 Lb = win(b);
     if (BORDER && Lb.w == 0.0f) continue;
 #pragma unroll
     for (int q = 0; q < P; ++q) {
@@ -476,7 +505,7 @@ __device__ __forceinline__ void search_tile(const ImgDesc& d, int ty, int tx, fl
     const int y = qy0 * s + ry, x = qx0 * s + rx;
     if (y >= d.H || x >= d.W) continue;
     const int cy = ry / s, cx = rx / s;
-    const float4* win = sL + cy * lx + cx;
+    const LdsWin<KW> win{sL + cy * lx + cx, lx, kw};
     const float4* tab = sTab + (cy * tqx + cx) * tstride;
     const bool full = interior || (x + P <= d.W);
 
@@ -486,19 +515,19 @@ __device__ __forceinline__ void search_tile(const ImgDesc& d, int ty, int tx, fl
     int code[P];
     if (MODE == MODE_EXH) {
       if (interior) {
-        exh_strip<KW, P, false, TABLE>(ip, win, lx, tab, eps, kw, best, code);
+        exh_strip<KW, P, false, TABLE>(ip, win, tab, eps, kw, best, code);
 #pragma unroll
-        for (int q = 0; q < P; ++q) al[q] = exh_alpha<KW, TABLE>(ip[q], win, lx, tab, eps, kw, code[q]);
+        for (int q = 0; q < P; ++q) al[q] = exh_alpha<KW, TABLE>(ip[q], win, tab, eps, kw, code[q]);
       } else {
-        exh_strip<KW, P, true, false>(ip, win, lx, tab, eps, kw, best, code);
+        exh_strip<KW, P, true, false>(ip, win, tab, eps, kw, best, code);
 #pragma unroll
-        for (int q = 0; q < P; ++q) al[q] = exh_alpha<KW, false>(ip[q], win, lx, tab, eps, kw, code[q]);
+        for (int q = 0; q < P; ++q) al[q] = exh_alpha<KW, false>(ip[q], win, tab, eps, kw, code[q]);
       }
     } else {
       if (interior)
-        fast_strip<KW, P, false>(ip, win, lx, eps, kw, best, code, al);
+        fast_strip<KW, P, false>(ip, win, eps, kw, best, code, al);
       else
-        fast_strip<KW, P, true>(ip, win, lx, eps, kw, best, code, al);
+        fast_strip<KW, P, true>(ip, win, eps, kw, best, code, al);
     }
     float e[P];
 #pragma unroll

@@ -179,10 +179,10 @@ def theta_expand(theta: Theta, s: int, k: int = 3):
     return a, b
 
 
-def apply_backward_workspace(H: int, W: int, C: int, s: int, k: int = 3) -> int:
+def apply_backward_workspace(H: int, W: int, channels: int, s: int, k: int = 3) -> int:
     lib = L.load()
     p = _params(s, k, EPS)
-    return int(lib.glu_apply_backward_workspace(int(H), int(W), int(C), C.byref(p)))
+    return int(lib.glu_apply_backward_workspace(int(H), int(W), int(channels), C.byref(p)))
 
 
 def apply_backward(theta: Theta, T_low, grad_T_hat, s, k=3, need_T_low=True, need_alpha=True, workspace=None,
