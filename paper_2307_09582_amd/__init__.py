@@ -16,6 +16,8 @@ from .glu import (  # noqa: F401
     downsample,
     empty_theta,
     glu_apply_autograd,
+    joint_downsample,
+    joint_downsample_workspace,
     lr_shape,
     search,
     search_apply,

@@ -5,13 +5,6 @@ using namespace glu;
 
 extern "C" {
 
-size_t glu_joint_downsample_workspace(int32_t, int32_t, const glu_params*) { return 0; }
-
-glu_status glu_joint_downsample(const glu_image*, glu_image*, const glu_params*, float, int32_t, glu_theta*, float*,
-                                void*, size_t, glu_jd_stats*, glu_jd_log*, void*) {
-  return fail(GLU_ERR_UNSUPPORTED, "glu_joint_downsample not built");
-}
-
 glu_status glu_batch_plan_create(const glu_batch_item*, int32_t, const glu_params*, glu_batch_plan**) {
   return fail(GLU_ERR_UNSUPPORTED, "batch plans not built");
 }

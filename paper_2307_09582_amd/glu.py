@@ -220,6 +220,77 @@ def apply_backward(theta: Theta, T_low, grad_T_hat, s, k=3, need_T_low=True, nee
     return gT, ga
 
 
+def joint_downsample_workspace(H: int, W: int, s: int, k: int = 3) -> int:
+    lib = L.load()
+    p = _params(s, k, EPS)
+    return int(lib.glu_joint_downsample_workspace(int(H), int(W), C.byref(p)))
+
+
+def joint_downsample(I, I_low0, s, k=3, eps=EPS, mode="exhaustive", tau=TAU, max_iter=N_ITER, log_capacity=None,
+                     q_capacity=None, workspace=None):
+    """Algorithm 2 (joint down/upsampling).  Returns (I_low, Theta, E, stats, log).
+
+    I_low0 is not modified (a copy is optimised).  stats is a dict of the
+    per-round counts; log a list of per-trial dicts in the sequential order.
+    """
+    H, W = I.shape[:2]
+    I_low = I_low0.clone()
+    theta = empty_theta(H, W, I.device)
+    err = torch.empty((H, W), dtype=torch.float32, device=I.device)
+    p = _params(s, k, eps, mode)
+    lib = L.load()
+    ws_bytes = int(lib.glu_joint_downsample_workspace(H, W, C.byref(p)))
+    if workspace is None or workspace.numel() * workspace.element_size() < ws_bytes:
+        workspace = torch.empty(max(1, ws_bytes), dtype=torch.uint8, device=I.device)
+    st = L.glu_jd_stats()
+    cap = int(log_capacity if log_capacity is not None else max(1024, H * W // 16))
+    qcap = int(q_capacity if q_capacity is not None else 4 * cap)
+    arrs = dict(
+        round=(C.c_int32 * cap)(), first_pixel=(C.c_int32 * cap)(), accepted=(C.c_uint8 * cap)(),
+        e0=(C.c_double * cap)(), e1=(C.c_double * cap)(), n_q=(C.c_int32 * cap)(),
+        q_and_pstar=(C.c_int64 * (2 * qcap))(),
+    )
+    lg = L.glu_jd_log(cap, 0, arrs["round"], arrs["first_pixel"], arrs["accepted"], arrs["e0"], arrs["e1"],
+                      arrs["n_q"], qcap, arrs["q_and_pstar"], 0)
+    L.check(
+        lib.glu_joint_downsample(
+            C.byref(_img(I, "I")),
+            C.byref(_img(I_low, "I_low")),
+            C.byref(p),
+            float(tau),
+            int(max_iter),
+            C.byref(_theta(theta)),
+            C.c_void_p(err.data_ptr() if err.numel() else None),
+            C.c_void_p(workspace.data_ptr()),
+            ws_bytes,
+            C.byref(st),
+            C.byref(lg),
+            _stream(),
+        )
+    )
+    n = st.rounds_run
+    stats = dict(
+        rounds_run=n,
+        n_large=list(st.n_large[:n]),
+        n_components=list(st.n_components[:n]),
+        n_accepted=list(st.n_accepted[:n]),
+        n_waves=list(st.n_waves[:n]),
+        err_sum_initial=st.err_sum_initial,
+        err_sum_final=st.err_sum_final,
+    )
+    log = []
+    qo = 0
+    for i in range(lg.count):
+        nq = arrs["n_q"][i]
+        pairs = [(int(arrs["q_and_pstar"][2 * (qo + j)]), int(arrs["q_and_pstar"][2 * (qo + j) + 1])) for j in range(nq)]
+        qo += nq
+        log.append(dict(round=arrs["round"][i], first_pixel=arrs["first_pixel"][i], accepted=bool(arrs["accepted"][i]),
+                        e0=arrs["e0"][i], e1=arrs["e1"][i], q_pstar=pairs))
+    if lg.truncated:
+        stats["log_truncated"] = True
+    return I_low, theta, err, stats, log
+
+
 class GluApply(torch.autograd.Function):
     """Eq. 1 as an autograd function of (alpha, T_low); the codes are constant.
 
