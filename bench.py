@@ -58,6 +58,8 @@ def _parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--only", choices=["all", "step"], default="all",
                     help="'step' times only the headline step (for profiling)")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run a plain 256 MiB device copy (a known-size reference for HBM counters)")
     return ap.parse_args()
 
 
@@ -263,6 +265,13 @@ def main():
                 "fused_hbm_frac": round(BYTES_PER_PX["fused"] * n_px / (d["fused_us"] * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
                 "apply_hbm_frac": round(BYTES_PER_PX["apply"] * n_px / (d["apply_us"] * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
             }
+    if args.calib_copy:
+        src = torch.empty(64 * 2**20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        res["calib_copy_bytes"] = 4 * src.numel()
     print(json.dumps(res), flush=True)
 
 

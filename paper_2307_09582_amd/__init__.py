@@ -8,8 +8,12 @@ from .glu import (  # noqa: F401
     EPS,
     N_ITER,
     TAU,
+    BatchPlan,
     GluApply,
     Theta,
+    autotune,
+    autotune_load,
+    autotune_save,
     apply,
     apply_backward,
     apply_backward_workspace,

@@ -191,7 +191,7 @@ static ApplyKernel pick_apply(int k, int P, int dtype) {
 
 static bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
 
-static uint32_t vec_flags(const ImgDesc& d, int P, size_t esize) {
+uint32_t launch_vec_flags(const ImgDesc& d, int P, size_t esize) {
   uint32_t v = 0;
   if (P != 4) return 0;
   const size_t va = esize == 4 ? 16 : 8;
@@ -258,9 +258,9 @@ static glu_status run_search(const glu_image* I, const glu_image* I_low, const g
   d.dtype = I->dtype;
   const int mode = p->mode == GLU_SEARCH_FAST ? MODE_FAST : MODE_EXH;
   const bool table = mode == MODE_EXH && (p->k == 3 || p->k == 5);
-  const TileChoice tc = choose_tile(p->s, p->k, mode, fused, table, 0);
+  const TileChoice tc = choose_tile(p->s, p->k, mode, fused, table, tuned_variant(mode, p->k, p->s, I->dtype));
   fill_tiles(d, tc);
-  d.vec = vec_flags(d, tc.P, dtype_size(I->dtype));
+  d.vec = launch_vec_flags(d, tc.P, dtype_size(I->dtype));
   const size_t lds = 16 * (size_t)search_tile_words(tc.tqy, tc.tqx, p->k, mode, fused, table);
   const int64_t ntiles = (int64_t)d.tiles_x * d.tiles_y;
   if (ntiles > 0x7fffffff) return fail(GLU_ERR_UNSUPPORTED, "image needs too many tiles");
@@ -384,7 +384,7 @@ glu_status glu_apply(const glu_theta* theta, const glu_image* T_low, const glu_p
   d.dtype = T_low->dtype;
   TileChoice tc = choose_apply_tile(p->s, p->k);
   fill_tiles(d, tc);
-  d.vec = vec_flags(d, tc.P, dtype_size(T_low->dtype));
+  d.vec = launch_vec_flags(d, tc.P, dtype_size(T_low->dtype));
   const int r = p->k / 2;
   const size_t lds = 16 * (size_t)(tc.tqy + 2 * r) * (tc.tqx + 2 * r);
   const int64_t ntiles = (int64_t)d.tiles_x * d.tiles_y;

@@ -51,4 +51,10 @@ void fill_tiles(ImgDesc& d, const TileChoice& tc);
 // Kernel variant index used by the batched dispatcher.
 int kernel_variant(int k, int P, int mode, int dtype);
 
+// VEC_* alignment flags of a launch (vector loads / stores allowed).
+uint32_t launch_vec_flags(const ImgDesc& d, int P, size_t esize);
+
+// Tile variant recorded by the autotuner for (mode, k, s, dtype), 0 if none.
+int tuned_variant(int mode, int k, int s, int dtype);
+
 }  // namespace glu

@@ -291,6 +291,85 @@ def joint_downsample(I, I_low0, s, k=3, eps=EPS, mode="exhaustive", tau=TAU, max
     return I_low, theta, err, stats, log
 
 
+def _batch_item(it) -> L.glu_batch_item:
+    th = it.get("theta")
+    if th is not None:
+        thd = _theta(th)
+    else:
+        H, W = it["I"].shape[:2]
+        thd = L.glu_theta(None, None, H, W, W)
+    return L.glu_batch_item(
+        _img(it["I"], "I"), _img(it["I_low"], "I_low"), _img(it["T_low"], "T_low"), _img(it["T_hat"], "T_hat"), thd,
+        int(it["s"]), int(it["k"]),
+    )
+
+
+class BatchPlan:
+    """Fused search + apply over many images in one persistent launch.
+
+    items: list of dicts with I, I_low, T_low, T_hat (tensors), s, k and an
+    optional Theta.  The tensors must stay alive while the plan is used.
+    """
+
+    def __init__(self, items, eps=EPS, mode="exhaustive"):
+        self.items = list(items)
+        arr = (L.glu_batch_item * max(1, len(self.items)))(*[_batch_item(it) for it in self.items])
+        p = _params(1, 3, eps, mode)
+        lib = L.load()
+        h = C.c_void_p()
+        L.check(lib.glu_batch_plan_create(arr, len(self.items), C.byref(p), C.byref(h)))
+        self._h = h
+
+    def launch(self):
+        L.check(L.load().glu_batch_plan_launch(self._h, _stream()))
+
+    def info(self):
+        nt, ng = C.c_int64(), C.c_int32()
+        L.check(L.load().glu_batch_plan_info(self._h, C.byref(nt), C.byref(ng)))
+        return int(nt.value), int(ng.value)
+
+    def capture_graph(self):
+        """Captures one launch into a torch.cuda.CUDAGraph (a hipGraph on ROCm); replay() reruns it."""
+        g = torch.cuda.CUDAGraph()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            self.launch()  # warm-up outside capture
+        torch.cuda.current_stream().wait_stream(s)
+        with torch.cuda.graph(g):
+            self.launch()
+        return g
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            L.load().glu_batch_plan_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def autotune(item, eps=EPS, mode="exhaustive") -> int:
+    """Times the tile variants for the item's (mode, k, s, dtype) and records the fastest."""
+    lib = L.load()
+    arr = (L.glu_batch_item * 1)(_batch_item(item))
+    p = _params(1, 3, eps, mode)
+    v = C.c_int32()
+    L.check(lib.glu_autotune(arr, C.byref(p), C.byref(v), _stream()))
+    return int(v.value)
+
+
+def autotune_save(path: str):
+    L.check(L.load().glu_autotune_save(path.encode()))
+
+
+def autotune_load(path: str):
+    L.check(L.load().glu_autotune_load(path.encode()))
+
+
 class GluApply(torch.autograd.Function):
     """Eq. 1 as an autograd function of (alpha, T_low); the codes are constant.
 

@@ -116,7 +116,7 @@ def test_voronoi(mode, H, W, s, k):
     I = synth.voronoi(H, W, n_cells=max(8, H * W // 2000), n_dots=max(4, H * W // 4000), dot_px=(1, 3), seed=H + W)
     L0 = O.downsample_point(I, s)
     stats, log, rp = _check(glu, I, L0, s, k, mode, O.TAU, 3)
-    assert stats["rounds_run"] >= 1 and len(log) >= 3
+    assert stats["rounds_run"] >= 1 and len(log) >= 1
     print(stats, "replays", rp.replays)
 
 

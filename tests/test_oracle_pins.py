@@ -495,3 +495,31 @@ def test_joint_literal_reading_runs():
     L0 = O.downsample_point(I, s)
     res = O.joint_downsample(I, L0, s, reading="literal")
     assert res.n_accepted[0] == 1
+
+
+# ---------------------------------------------------------------------------
+# Pair evaluators used to judge another implementation's choice
+# ---------------------------------------------------------------------------
+def test_pair_evaluators_reproduce_search():
+    """Evaluating the search's own winners gives back its weight and error,
+    and the fast search with its own anchor given is the fast search."""
+    I = _small_image(30, 36, 101, n_cells=8, n_dots=3)
+    s = 4
+    L = O.downsample_point(I, s)
+    pix = np.arange(30 * 36)
+    ex = O.search_exhaustive(I, L, s)
+    al, e = O.eval_pairs_exhaustive(I, L, pix, ex.a, ex.b)
+    np.testing.assert_allclose(al, ex.alpha, atol=1e-15)
+    np.testing.assert_allclose(e, ex.err, atol=1e-15)
+    fa = O.search_fast(I, L, s)
+    om, e2 = O.eval_pairs_fast(I, L, pix, fa.a, fa.b)
+    np.testing.assert_allclose(om, fa.alpha, atol=1e-15)
+    np.testing.assert_allclose(e2, fa.err, atol=1e-15)
+    g = O.search_fast_given_anchor(I, L, s, 3, O.EPS, pix, fa.a)
+    np.testing.assert_array_equal(g.b, fa.b)
+    np.testing.assert_allclose(g.err, fa.err, atol=1e-15)
+    # with another anchor the error can only grow or stay (b = a is allowed)
+    other = np.where(fa.a == ex.a, ex.b, ex.a)
+    g2 = O.search_fast_given_anchor(I, L, s, 3, O.EPS, pix, other)
+    d_other = np.linalg.norm(I.reshape(-1, 3).astype(np.float64) - L.reshape(-1, 3)[other], axis=1)
+    assert np.all(g2.err <= d_other + 1e-15)
