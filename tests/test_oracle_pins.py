@@ -523,3 +523,39 @@ def test_pair_evaluators_reproduce_search():
     g2 = O.search_fast_given_anchor(I, L, s, 3, O.EPS, pix, other)
     d_other = np.linalg.norm(I.reshape(-1, 3).astype(np.float64) - L.reshape(-1, 3)[other], axis=1)
     assert np.all(g2.err <= d_other + 1e-15)
+
+
+def test_exact_ties_go_to_the_earliest_candidate():
+    """Reading of the tie rule: the first candidate in colexicographic order
+    wins an exact tie (exhaustive), and the anchor is the first cell of least
+    distance (fast).  Cells 0 and 4 of the window carry the same colour, equal
+    to the pixel: (0, 0) comes before every other zero-error candidate."""
+    L = np.zeros((3, 3, 3))
+    L[..., 0] = np.arange(9).reshape(3, 3) / 9.0
+    L[..., 1] = 0.3
+    L[1, 1] = L[0, 0]
+    I = np.repeat(np.repeat(L, 2, 0), 2, 1)
+    p = 1 * 6 + 2  # pixel (1, 2): its window is the whole 3 x 3 LR image, centre cell 4
+    I[1, 2] = L[0, 0]
+    ex = O.search_exhaustive(I, L, 2, 3, O.EPS, pixels=[p])
+    assert (int(ex.a[0]), int(ex.b[0])) == (0, 0) and ex.err[0] == 0.0
+    fa = O.search_fast(I, L, 2, 3, O.EPS, pixels=[p])
+    assert int(fa.a[0]) == 0 and int(fa.b[0]) == 0
+
+
+def test_joint_replacement_takes_the_largest_error():
+    """Alg. 2 replaces I_down[q] by the pixel of [q_up] & C with the largest
+    error: a two-colour dot whose brighter pixel is farther from the
+    background puts that colour into I_down."""
+    s = 8
+    I = np.empty((64, 64, 3))
+    I[:] = (0.4, 0.5, 0.6)
+    far, near = (0.95, 0.05, 0.05), (0.75, 0.35, 0.35)
+    # off the block's sampling point (20, 20), so neither colour is in I_down
+    I[18, 18] = near
+    I[18, 19] = far
+    L0 = O.downsample_point(I, s)
+    res = O.joint_downsample(I, L0, s, tau=O.TAU, max_iter=1)
+    d = res.log[0]
+    assert d.q_pstar == [(2 * 8 + 2, 18 * 64 + 19)]
+    assert np.array_equal(res.L[2, 2], np.array(far))
