@@ -108,17 +108,6 @@ TileChoice choose_tile(int s, int k, int mode, bool fused, bool table, int varia
   return tc;
 }
 
-TileChoice choose_apply_tile(int s, int k) {
-  TileChoice tc;
-  tc.P = (s % 4 == 0) ? 4 : 1;
-  tc.tqx = std::max(1, 64 / s);
-  const int rows = std::max(1, kApplyStrips * kThreads * tc.P / (tc.tqx * s));
-  tc.tqy = std::max(1, rows / s);
-  const int r = k / 2;
-  while (16 * (tc.tqy + 2 * r) * (tc.tqx + 2 * r) > kLdsBudget && tc.tqy > 1) tc.tqy = (tc.tqy + 1) / 2;
-  return tc;
-}
-
 void fill_tiles(ImgDesc& d, const TileChoice& tc) {
   d.tqy = tc.tqy;
   d.tqx = tc.tqx;
@@ -143,16 +132,15 @@ __global__ __launch_bounds__(kThreads) void k_search(const ImgDesc d, float eps)
   search_tile<KW, P, MODE, T, FUSED, (MODE == MODE_EXH && KW > 0)>(d, ty, tx, eps, smem);
 }
 
+// One workgroup per run of kThreads * kApplyStrips strips of one HR row.
 template <int KW, int P, typename T>
-__global__ __launch_bounds__(kThreads) void k_apply(const ImgDesc d) {
-  extern __shared__ float4 smem[];
-  const int tile = blockIdx.x;
-  const int ty = tile / d.tiles_x, tx = tile - ty * d.tiles_x;
-  apply_tile<KW, P, T, kApplyStrips>(d, ty, tx, smem);
+__global__ __launch_bounds__(kThreads) void k_apply(const ImgDesc d, int runs, uint32_t s_magic) {
+  const int y = blockIdx.x / runs, run = blockIdx.x - y * runs;
+  apply_row_run<KW, P, T, kApplyStrips>(d, y, run, s_magic);
 }
 
 typedef void (*SearchKernel)(const ImgDesc, float);
-typedef void (*ApplyKernel)(const ImgDesc);
+typedef void (*ApplyKernel)(const ImgDesc, int, uint32_t);
 
 template <int KW, int P, typename T>
 static SearchKernel pick_search_t(int mode, bool fused) {
@@ -382,15 +370,14 @@ glu_status glu_apply(const glu_theta* theta, const glu_image* T_low, const glu_p
   d.k = p->k;
   d.C = T_low->channels;
   d.dtype = T_low->dtype;
-  TileChoice tc = choose_apply_tile(p->s, p->k);
-  fill_tiles(d, tc);
-  d.vec = launch_vec_flags(d, tc.P, dtype_size(T_low->dtype));
-  const int r = p->k / 2;
-  const size_t lds = 16 * (size_t)(tc.tqy + 2 * r) * (tc.tqx + 2 * r);
-  const int64_t ntiles = (int64_t)d.tiles_x * d.tiles_y;
-  if (ntiles > 0x7fffffff) return fail(GLU_ERR_UNSUPPORTED, "image needs too many tiles");
-  ApplyKernel kern = pick_apply(p->k, tc.P, T_low->dtype);
-  hipLaunchKernelGGL(kern, dim3((unsigned)ntiles), dim3(kThreads), lds, (hipStream_t)stream, d);
+  const int P = (p->s % 4 == 0) ? 4 : 1;
+  d.vec = launch_vec_flags(d, P, dtype_size(T_low->dtype));
+  const int runs = ceil_div(W, P * kThreads * kApplyStrips);
+  const int64_t groups = (int64_t)runs * H;
+  if (groups > 0x7fffffff) return fail(GLU_ERR_UNSUPPORTED, "image too large");
+  const uint32_t s_magic = (uint32_t)std::min<uint64_t>(0xffffffffull, (1ull << 32) / (uint64_t)p->s);
+  ApplyKernel kern = pick_apply(p->k, P, T_low->dtype);
+  hipLaunchKernelGGL(kern, dim3((unsigned)groups), dim3(kThreads), 0, (hipStream_t)stream, d, runs, s_magic);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "apply launch");
   return GLU_OK;

@@ -11,9 +11,10 @@
 //   pass 1 (HR stream, one read of G and Theta): for every LR cell c and
 //     every window offset o, S[c][o] = sum over the pixels of c's s x s
 //     block, in raster order, of the part of their contribution aimed at the
-//     cell c + offset(o).  One thread owns one (c, o) pair and scans the
-//     block's pixels from LDS in a fixed order.  The same pass writes
-//     dL/dalpha.
+//     cell c + offset(o).  A workgroup owns nb consecutive cells of one LR
+//     row: it streams their s HR rows (vector loads, dL/dalpha written on
+//     the way) into LDS, then one thread per (cell, o) scans the block's
+//     pixels in raster order.
 //   pass 2 (LR): dT_low[q] = sum over o in ascending order of
 //     S[q - offset(o)][o].
 //
@@ -40,47 +41,65 @@ struct BwdArgs {
   int32_t H, W, h, w, s, k, C;
   int32_t nb;           // LR cells per workgroup (one LR row)
   int32_t rows_chunk;   // HR rows staged per chunk
+  int32_t groups_x;     // workgroups per LR row
+  uint32_t s_magic;     // floor(2^32 / s) for udiv_rt
+  uint32_t vec;         // VEC_THETA | VEC_G | VEC_T(dalpha rows)
 };
 
-// LDS layout of pass 1: staged T_low cells (float4), then per staged pixel a
-// packed code word, alpha, and C gradient values (SoA).
-template <typename T>
+// Loads C <= 4 gradient channels of pixels x .. x+P-1 (vector path for
+// P = 4, C = 3 or 1 on aligned rows).
+template <int P>
+__device__ __forceinline__ void load_grad(const float* __restrict__ row, int x, int W, int C, bool vec, bool full,
+                                          float (&g)[P][4]) {
+  const float* p = row + (int64_t)x * C;
+  if constexpr (P == 4) {
+    if (vec && full && C == 3) {
+      const float4* q = reinterpret_cast<const float4*>(p);
+      const float4 a = q[0], b = q[1], c = q[2];
+      g[0][0] = a.x; g[0][1] = a.y; g[0][2] = a.z;
+      g[1][0] = a.w; g[1][1] = b.x; g[1][2] = b.y;
+      g[2][0] = b.z; g[2][1] = b.w; g[2][2] = c.x;
+      g[3][0] = c.y; g[3][1] = c.z; g[3][2] = c.w;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) g[i][3] = 0.f;
+      return;
+    }
+    if (vec && full && C == 1) {
+      const float4 a = *reinterpret_cast<const float4*>(p);
+      g[0][0] = a.x; g[1][0] = a.y; g[2][0] = a.z; g[3][0] = a.w;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) g[i][1] = g[i][2] = g[i][3] = 0.f;
+      return;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < P; ++i) {
+    const bool ok = full || (x + i < W);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) g[i][c] = (ok && c < C) ? p[i * C + c] : 0.f;
+  }
+}
+
+// LDS layout of pass 1 for one chunk of HR rows of the group: per pixel slot
+// a packed code word (o_a | o_b << 8), alpha, and C gradient values (SoA).
+template <typename T, int P>
 __global__ __launch_bounds__(kThreads) void k_bwd_block(const BwdArgs a) {
   extern __shared__ float4 smem[];
   const int k = a.k, r = k / 2, K2 = k * k, s = a.s, C = a.C;
-  const int groups_x = (a.w + a.nb - 1) / a.nb;
-  const int qy = blockIdx.x / groups_x;
-  const int qx0 = (blockIdx.x - qy * groups_x) * a.nb;
+  const int qy = blockIdx.x / a.groups_x;
+  const int qx0 = (blockIdx.x - qy * a.groups_x) * a.nb;
   const int nb = min(a.nb, a.w - qx0);
-  const int ly = 1 + 2 * r, lx = nb + 2 * r;
-  float4* sT = smem;                                       // ly * lx cells
-  const int chunk_px = a.rows_chunk * a.nb * s;            // pixel slots per chunk
-  int* sCode = reinterpret_cast<int*>(sT + ly * lx);       // chunk_px
-  float* sAl = reinterpret_cast<float*>(sCode + chunk_px);  // chunk_px
-  float* sG = sAl + chunk_px;                              // C * chunk_px
-
-  // stage the T_low cells the chunk's pixels can reach (for dalpha)
-  if (a.dalpha) {
-    const T* TL = static_cast<const T*>(a.T);
-    for (int c = threadIdx.x; c < ly * lx; c += kThreads) {
-      const int oy = c / lx;
-      const int cy = qy - r + oy, cx = qx0 - r + (c - oy * lx);
-      float tt[4] = {0.f, 0.f, 0.f, 0.f};
-      if (cy >= 0 && cy < a.h && cx >= 0 && cx < a.w) {
-        const T* q = TL + (int64_t)cy * a.T_stride + (int64_t)cx * C;
-#pragma unroll
-        for (int ch = 0; ch < 4; ++ch)
-          if (ch < C) tt[ch] = to_f<T>(q[ch]);
-      }
-      sT[c] = make_float4(tt[0], tt[1], tt[2], tt[3]);
-    }
-    __syncthreads();
-  }
+  const int chunk_px = a.rows_chunk * a.nb * s;  // pixel slots per chunk
+  int* sCode = reinterpret_cast<int*>(smem);
+  float* sAl = reinterpret_cast<float*>(sCode + chunk_px);
+  float* sG = sAl + chunk_px;  // C * chunk_px
+  const T* __restrict__ TL = static_cast<const T*>(a.T);
+  const bool vecTh = (a.vec & VEC_THETA) != 0, vecG = (a.vec & VEC_G) != 0, vecA = (a.vec & VEC_T) != 0;
 
   const int y0 = qy * s, y1 = min(a.H, y0 + s);
   const int x0 = qx0 * s, x1 = min(a.W, x0 + nb * s);
-  const int seg = x1 - x0;  // pixels per HR row of the group
-  // phase-2 ownership: thread -> (cell, offset)
+  const int seg = x1 - x0;             // pixels per HR row of the group
+  const int spr = (seg + P - 1) / P;   // strips per HR row of the group
   const int n_pairs_grp = nb * K2;
   float acc[2][4];
 #pragma unroll
@@ -90,36 +109,81 @@ __global__ __launch_bounds__(kThreads) void k_bwd_block(const BwdArgs a) {
 
   for (int yc = y0; yc < y1; yc += a.rows_chunk) {
     const int yce = min(y1, yc + a.rows_chunk);
-    const int npx = (yce - yc) * seg;
-    // load the chunk: code, alpha, G; write dalpha
-    for (int i = threadIdx.x; i < npx; i += kThreads) {
-      const int ry = i / seg, rx = i - ry * seg;
+    const int nstrips = (yce - yc) * spr;
+    for (int t = threadIdx.x; t < nstrips; t += kThreads) {
+      const int ry = t / spr;
+      const int rx = (t - ry * spr) * P;
       const int y = yc + ry, x = x0 + rx;
+      const bool full = rx + P <= seg;
       const int64_t to = (int64_t)y * a.th_stride + x;
-      const int cd = a.code[to];
-      const float al = a.alpha[to];
-      const float* g = a.G + (int64_t)y * a.G_stride + (int64_t)x * C;
-      float gv[4] = {0.f, 0.f, 0.f, 0.f};
+      int cd[P];
+      float al[P];
+      bool done = false;
+      if constexpr (P == 4) {
+        if (vecTh && full) {
+          const u32x2 c = __builtin_nontemporal_load(reinterpret_cast<const u32x2*>(a.code + to));
+          const f32x4 a4 = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(a.alpha + to));
+          cd[0] = c.x & 0xffff;
+          cd[1] = c.x >> 16;
+          cd[2] = c.y & 0xffff;
+          cd[3] = c.y >> 16;
+          al[0] = a4.x;
+          al[1] = a4.y;
+          al[2] = a4.z;
+          al[3] = a4.w;
+          done = true;
+        }
+      }
+      if (!done) {
 #pragma unroll
-      for (int ch = 0; ch < 4; ++ch)
-        if (ch < C) gv[ch] = g[ch];
-      const int cdc = min(cd, K2 * K2 - 1);
-      const int oa = cdc / K2, ob = cdc - oa * K2;
-      // slot in the chunk: row-major over (row, x)
-      sCode[i] = oa | (ob << 8);
-      sAl[i] = al;
+        for (int q = 0; q < P; ++q) {
+          const bool ok = full || (rx + q < seg);
+          cd[q] = ok ? a.code[to + q] : 0;
+          al[q] = ok ? a.alpha[to + q] : 0.f;
+        }
+      }
+      float g[P][4];
+      load_grad<P>(a.G + (int64_t)y * a.G_stride, x, a.W, C, vecG, full, g);
+      const int qx = udiv_rt(x, s, a.s_magic);  // all P pixels share it
+      float da[P];
 #pragma unroll
-      for (int ch = 0; ch < 4; ++ch)
-        if (ch < C) sG[ch * chunk_px + i] = gv[ch];
+      for (int q = 0; q < P; ++q) {
+        const int cdc = min(cd[q], K2 * K2 - 1);
+        const int oa = cdc / K2, ob = cdc - oa * K2;
+        const int i = ry * seg + rx + q;
+        if (full || rx + q < seg) {
+          sCode[i] = oa | (ob << 8);
+          sAl[i] = al[q];
+#pragma unroll
+          for (int ch = 0; ch < 4; ++ch)
+            if (ch < C) sG[ch * chunk_px + i] = g[q][ch];
+        }
+        da[q] = 0.f;
+        if (a.dalpha && (full || rx + q < seg)) {
+          const int ay = min(max(qy + oa / k - r, 0), a.h - 1), ax = min(max(qx + oa % k - r, 0), a.w - 1);
+          const int by = min(max(qy + ob / k - r, 0), a.h - 1), bx = min(max(qx + ob % k - r, 0), a.w - 1);
+          const float4 Ta = load_cell<T>(TL + (int64_t)ay * a.T_stride + (int64_t)ax * C, C);
+          const float4 Tb = load_cell<T>(TL + (int64_t)by * a.T_stride + (int64_t)bx * C, C);
+          float v = g[q][0] * (Ta.x - Tb.x);
+          if (C > 1) v = fmaf(g[q][1], Ta.y - Tb.y, v);
+          if (C > 2) v = fmaf(g[q][2], Ta.z - Tb.z, v);
+          if (C > 3) v = fmaf(g[q][3], Ta.w - Tb.w, v);
+          da[q] = v;
+        }
+      }
       if (a.dalpha) {
-        const int cx = x / s - qx0;  // cell within the group
-        const float4 Ta = sT[(oa / k) * lx + cx + oa % k];
-        const float4 Tb = sT[(ob / k) * lx + cx + ob % k];
-        float da = gv[0] * (Ta.x - Tb.x);
-        if (C > 1) da = fmaf(gv[1], Ta.y - Tb.y, da);
-        if (C > 2) da = fmaf(gv[2], Ta.z - Tb.z, da);
-        if (C > 3) da = fmaf(gv[3], Ta.w - Tb.w, da);
-        a.dalpha[to] = da;
+        bool st = false;
+        if constexpr (P == 4) {
+          if (vecA && full) {
+            *reinterpret_cast<float4*>(a.dalpha + to) = make_float4(da[0], da[1], da[2], da[3]);
+            st = true;
+          }
+        }
+        if (!st) {
+#pragma unroll
+          for (int q = 0; q < P; ++q)
+            if (full || rx + q < seg) a.dalpha[to + q] = da[q];
+        }
       }
     }
     __syncthreads();
@@ -136,8 +200,8 @@ __global__ __launch_bounds__(kThreads) void k_bwd_block(const BwdArgs a) {
             const int i = ry * seg + rx;
             const int pk = sCode[i];
             const int oa = pk & 0xff, ob = pk >> 8;
-            const float al = sAl[i];
             if (oa == o || ob == o) {
+              const float al = sAl[i];
               float wgt = (oa == o) ? al : 0.0f;
               wgt = (ob == o) ? wgt + (1.0f - al) : wgt;
 #pragma unroll
@@ -191,8 +255,7 @@ static void bwd_geometry(int s, int k, int C, int w, int& nb, int& rows_chunk) {
   // limit the cells of a group so one HR row of it stays within a few strips
   nb = std::min(nb, std::max(1, 512 / s));
   const int bytes_per_px = 4 * (2 + C);
-  const int r = k / 2;
-  auto lds = [&](int n, int rc) { return 16 * (1 + 2 * r) * (n + 2 * r) + bytes_per_px * rc * n * s; };
+  auto lds = [&](int n, int rc) { return bytes_per_px * rc * n * s; };
   rows_chunk = s;
   while (rows_chunk > 1 && lds(nb, rows_chunk) > kLdsBudget) rows_chunk = (rows_chunk + 1) / 2;
   while (nb > 1 && lds(nb, rows_chunk) > kLdsBudget) nb = (nb + 1) / 2;
@@ -235,9 +298,7 @@ glu_status glu_apply_backward(const glu_theta* theta, const glu_image* T_low, co
       return fail(GLU_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
     if (reinterpret_cast<uintptr_t>(workspace) % 4) return fail(GLU_ERR_ALIGN, "workspace not aligned");
   }
-  if ((int64_t)H * W == 0) {
-    return GLU_OK;
-  }
+  if ((int64_t)H * W == 0) return GLU_OK;
   if (!grad_T_low && !grad_alpha) return GLU_OK;
   BwdArgs a{};
   a.code = theta->code;
@@ -259,15 +320,34 @@ glu_status glu_apply_backward(const glu_theta* theta, const glu_image* T_low, co
   a.k = p->k;
   a.C = C;
   bwd_geometry(p->s, p->k, C, w, a.nb, a.rows_chunk);
-  const int r = p->k / 2;
-  const size_t lds = 16 * (size_t)(1 + 2 * r) * (a.nb + 2 * r) + (size_t)4 * (2 + C) * a.rows_chunk * a.nb * p->s;
-  const int64_t groups = (int64_t)h * ceil_div(w, a.nb);
+  a.groups_x = ceil_div(w, a.nb);
+  a.s_magic = (uint32_t)std::min<uint64_t>(0xffffffffull, (1ull << 32) / (uint64_t)p->s);
+  const int P = (p->s % 4 == 0) ? 4 : 1;
+  {
+    // alignment of the vector paths (all with x a multiple of 4)
+    auto al = [](const void* q, size_t n) { return (reinterpret_cast<uintptr_t>(q) % n) == 0; };
+    uint32_t v = 0;
+    if (P == 4 && theta->row_stride % 4 == 0 && al(theta->code, 8) && al(theta->alpha, 16) &&
+        (!grad_alpha || al(grad_alpha, 16)))
+      v |= VEC_THETA | VEC_T;
+    if (P == 4 && (C == 3 || C == 1) && grad_T_hat->row_stride % 4 == 0 && al(grad_T_hat->data, 16)) v |= VEC_G;
+    a.vec = v;
+  }
+  const size_t lds = (size_t)4 * (2 + C) * a.rows_chunk * a.nb * p->s;
+  const int64_t groups = (int64_t)h * a.groups_x;
   if (groups > 0x7fffffff) return fail(GLU_ERR_UNSUPPORTED, "image too large");
   hipStream_t sm = (hipStream_t)stream;
-  if (T_low->dtype == GLU_F16)
-    hipLaunchKernelGGL(k_bwd_block<__half>, dim3((unsigned)groups), dim3(kThreads), lds, sm, a);
-  else
-    hipLaunchKernelGGL(k_bwd_block<float>, dim3((unsigned)groups), dim3(kThreads), lds, sm, a);
+  if (T_low->dtype == GLU_F16) {
+    if (P == 4)
+      hipLaunchKernelGGL((k_bwd_block<__half, 4>), dim3((unsigned)groups), dim3(kThreads), lds, sm, a);
+    else
+      hipLaunchKernelGGL((k_bwd_block<__half, 1>), dim3((unsigned)groups), dim3(kThreads), lds, sm, a);
+  } else {
+    if (P == 4)
+      hipLaunchKernelGGL((k_bwd_block<float, 4>), dim3((unsigned)groups), dim3(kThreads), lds, sm, a);
+    else
+      hipLaunchKernelGGL((k_bwd_block<float, 1>), dim3((unsigned)groups), dim3(kThreads), lds, sm, a);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "backward pass 1 launch");
   if (grad_T_low) {

@@ -553,105 +553,107 @@ __device__ __forceinline__ void search_tile(const ImgDesc& d, int ty, int tx, fl
 }
 
 // ---------------------------------------------------------------------------
-// One tile of apply (Eq. 1)
+// Apply (Eq. 1) over runs of one HR row
 // ---------------------------------------------------------------------------
-// Apply is a pure stream (6 bytes of Theta in, 4C bytes out per pixel), so a
-// thread owns NS strips and issues all their Theta loads before the LDS
-// staging barrier; the T_low window of the tile is staged once.
+// Apply is a pure stream (6 bytes of Theta in, 4C bytes out per pixel).  A
+// workgroup owns a run of kThreads * NS strips of P pixels of one HR row, so
+// its loads and stores are contiguous; the two LR cells of a pixel are
+// gathered straight from global memory (the LR target is small and stays
+// in the caches).  No LDS, no barrier.
+//
+// Unsigned division by a runtime divisor d < 2^16 for n < 2^31: the estimate
+// q = umulhi(n, floor(2^32 / d)) is floor(n / d) or one less; one
+// correction step makes it exact.
+__device__ __forceinline__ int udiv_rt(int n, int d, uint32_t m) {
+  int q = (int)__umulhi((uint32_t)n, m);
+  if ((q + 1) * d <= n) ++q;
+  return q;
+}
+
+template <typename T>
+__device__ __forceinline__ float4 load_cell(const T* __restrict__ p, int C) {
+  float v[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+    if (c < C) v[c] = to_f<T>(p[c]);
+  return make_float4(v[0], v[1], v[2], v[3]);
+}
+
 template <int KW, int P, typename T, int NS>
-__device__ __forceinline__ void apply_tile(const ImgDesc& d, int ty, int tx, float4* smem) {
+__device__ __forceinline__ void apply_row_run(const ImgDesc& d, int y, int run, uint32_t s_magic) {
   const int kw = KW > 0 ? KW : d.k;
   const int R = kw / 2;
   const int K2 = kw * kw;
-  const int s = d.s;
-  const int tqy = d.tqy, tqx = d.tqx;
-  const int qy0 = ty * tqy, qx0 = tx * tqx;
-  const int ly = tqy + 2 * R, lx = tqx + 2 * R;
-  float4* sT = smem;
-  const int rows = tqy * s, cols = tqx * s;
-  const int spr = cols / P;
-  const int nstrips = rows * spr;
-  const bool interior = ((qy0 + tqy) * s <= d.H) && ((qx0 + tqx) * s <= d.W);
-  const bool vecTh = (d.vec & VEC_THETA) != 0, vecT = (d.vec & VEC_T) != 0;
   const int maxcode = K2 * K2 - 1;
-
-  for (int base = 0; base < nstrips; base += NS * kThreads) {
-    // strip coordinates: t = base + tid + n * kThreads, walked without divisions
-    int ry[NS], rx[NS];
-    {
-      const int t0 = base + threadIdx.x;
-      const int ry0 = t0 / spr;
-      const int dr = kThreads / spr, dc = kThreads - dr * spr;
-      int r0 = ry0, c0 = t0 - ry0 * spr;
+  const int s = d.s, C = d.C;
+  const bool vecTh = (d.vec & VEC_THETA) != 0, vecT = (d.vec & VEC_T) != 0;
+  const int qy = udiv_rt(y, s, s_magic);
+  const T* __restrict__ TL = static_cast<const T*>(d.T);
+  const int64_t trow = (int64_t)y * d.th_stride;
+  int code[NS][P];
+  float al[NS][P];
+  int xs[NS];
 #pragma unroll
-      for (int n = 0; n < NS; ++n) {
-        ry[n] = r0;
-        rx[n] = c0 * P;
-        r0 += dr;
-        c0 += dc;
-        if (c0 >= spr) {
-          c0 -= spr;
-          r0 += 1;
-        }
+  for (int n = 0; n < NS; ++n) {
+    const int x = ((run * NS + n) * kThreads + (int)threadIdx.x) * P;
+    xs[n] = x;
+    const bool live = x < d.W;
+    const bool full = x + P <= d.W;
+    const int64_t to = trow + x;
+    bool done = false;
+    if constexpr (P == 4) {
+      if (live && full && vecTh) {
+        const u32x2 c = __builtin_nontemporal_load(reinterpret_cast<const u32x2*>(d.code + to));
+        const f32x4 a4 = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(d.alpha + to));
+        code[n][0] = c.x & 0xffff;
+        code[n][1] = c.x >> 16;
+        code[n][2] = c.y & 0xffff;
+        code[n][3] = c.y >> 16;
+        al[n][0] = a4.x;
+        al[n][1] = a4.y;
+        al[n][2] = a4.z;
+        al[n][3] = a4.w;
+        done = true;
       }
     }
-    int code[NS][P];
-    float al[NS][P];
-#pragma unroll
-    for (int n = 0; n < NS; ++n) {
-      const int y = qy0 * s + ry[n], x = qx0 * s + rx[n];
-      const bool live = (base + threadIdx.x + n * kThreads < nstrips) && y < d.H && x < d.W;
-      const bool full = interior || (x + P <= d.W);
-      const int64_t to = (int64_t)y * d.th_stride + x;
-      bool done = false;
-      if constexpr (P == 4) {
-        if (live && vecTh && full) {
-          const u32x2 c = __builtin_nontemporal_load(reinterpret_cast<const u32x2*>(d.code + to));
-          const f32x4 a4 = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(d.alpha + to));
-          code[n][0] = c.x & 0xffff;
-          code[n][1] = c.x >> 16;
-          code[n][2] = c.y & 0xffff;
-          code[n][3] = c.y >> 16;
-          al[n][0] = a4.x;
-          al[n][1] = a4.y;
-          al[n][2] = a4.z;
-          al[n][3] = a4.w;
-          done = true;
-        }
-      }
-      if (!done) {
-#pragma unroll
-        for (int q = 0; q < P; ++q) {
-          const bool ok = live && (full || (x + q < d.W));
-          code[n][q] = ok ? d.code[to + q] : 0;
-          al[n][q] = ok ? d.alpha[to + q] : 0.0f;
-        }
-      }
-    }
-    if (base == 0) {
-      stage_lr<T>(d, qy0, qx0, R, ly, lx, nullptr, sT);
-      __syncthreads();
-    }
-#pragma unroll
-    for (int n = 0; n < NS; ++n) {
-      const int y = qy0 * s + ry[n], x = qx0 * s + rx[n];
-      if (!((base + threadIdx.x + n * kThreads < nstrips) && y < d.H && x < d.W)) continue;
-      const bool full = interior || (x + P <= d.W);
-      const int cy = ry[n] / s, cx = rx[n] / s;
-      float o[P][4];
+    if (!done) {
 #pragma unroll
       for (int q = 0; q < P; ++q) {
-        const int cd = min(code[n][q], maxcode);
-        const int oa = cd / K2, ob = cd - oa * K2;
-        const float4 Ta = sT[(cy + oa / kw) * lx + cx + oa % kw];
-        const float4 Tb = sT[(cy + ob / kw) * lx + cx + ob % kw];
-        o[q][0] = fmaf(al[n][q], Ta.x - Tb.x, Tb.x);
-        o[q][1] = fmaf(al[n][q], Ta.y - Tb.y, Tb.y);
-        o[q][2] = fmaf(al[n][q], Ta.z - Tb.z, Tb.z);
-        o[q][3] = fmaf(al[n][q], Ta.w - Tb.w, Tb.w);
+        const bool ok = x + q < d.W;
+        code[n][q] = ok ? d.code[to + q] : 0;
+        al[n][q] = ok ? d.alpha[to + q] : 0.0f;
       }
-      store_out<T, P>(static_cast<T*>(d.That) + (int64_t)y * d.That_stride, x, d.W, d.C, vecT, full, o);
     }
+  }
+#pragma unroll
+  for (int n = 0; n < NS; ++n) {
+    const int x = xs[n];
+    if (x >= d.W) continue;
+    const bool full = x + P <= d.W;
+    // all P pixels of a strip share their LR cell (P divides s)
+    const int qx = udiv_rt(x, s, s_magic);
+    float o[P][4];
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+      const int cd = min(code[n][q], maxcode);
+      const int oa = cd / K2, ob = cd - oa * K2;
+      const int ay = qy + oa / kw - R, ax = qx + oa % kw - R;
+      const int by = qy + ob / kw - R, bx = qx + ob % kw - R;
+      float4 Ta = make_float4(0.f, 0.f, 0.f, 0.f), Tb = Ta;
+      if (x + q < d.W) {
+        // codes from the search always point inside the LR image; others
+        // are clamped so that the gather stays inside the buffer
+        const int ayc = min(max(ay, 0), d.h - 1), axc = min(max(ax, 0), d.w - 1);
+        const int byc = min(max(by, 0), d.h - 1), bxc = min(max(bx, 0), d.w - 1);
+        Ta = load_cell<T>(TL + (int64_t)ayc * d.T_stride + (int64_t)axc * C, C);
+        Tb = load_cell<T>(TL + (int64_t)byc * d.T_stride + (int64_t)bxc * C, C);
+      }
+      o[q][0] = fmaf(al[n][q], Ta.x - Tb.x, Tb.x);
+      o[q][1] = fmaf(al[n][q], Ta.y - Tb.y, Tb.y);
+      o[q][2] = fmaf(al[n][q], Ta.z - Tb.z, Tb.z);
+      o[q][3] = fmaf(al[n][q], Ta.w - Tb.w, Tb.w);
+    }
+    store_out<T, P>(static_cast<T*>(d.That) + (int64_t)y * d.That_stride, x, d.W, C, vecT, full, o);
   }
 }
 

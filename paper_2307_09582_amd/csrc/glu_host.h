@@ -42,8 +42,6 @@ struct TileChoice {
 // autotuner (0 = default).
 TileChoice choose_tile(int s, int k, int mode, bool fused, bool table, int variant);
 int n_tile_variants();
-// Tile of the apply kernel: strips of P pixels, kApplyStrips per thread.
-TileChoice choose_apply_tile(int s, int k);
 
 // Fills the image descriptor fields common to search / apply launches.
 void fill_tiles(ImgDesc& d, const TileChoice& tc);
