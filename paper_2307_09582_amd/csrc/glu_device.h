@@ -172,28 +172,38 @@ __device__ __forceinline__ void store_out(T* __restrict__ row, int x, int W, int
 // ---------------------------------------------------------------------------
 // Pair constants and weights
 // ---------------------------------------------------------------------------
-// For the window pair (i, j): e = L_i - L_j and 1 / (|e|^2 + eps) (Eq. 4);
-// 0 marks a zero denominator (eps = 0 and L_i == L_j), whose weight is 1.
-__device__ __forceinline__ float4 pair_consts(float4 Li, float4 Lj, float eps) {
+// For the window pair (i, j): e = L_i - L_j, inv = 1 / (|e|^2 + eps) and the
+// scaled direction e * inv (Eq. 4), so that the weight is one clamped dot
+// product.  inv = 0 marks a zero denominator (eps = 0 and L_i == L_j), whose
+// weight is 1.
+struct PairK {
+  float4 e;   // e.x, e.y, e.z, unused
+  float4 ei;  // e * inv (x, y, z), inv
+};
+
+__device__ __forceinline__ PairK pair_consts(float4 Li, float4 Lj, float eps) {
   const float ex = Li.x - Lj.x, ey = Li.y - Lj.y, ez = Li.z - Lj.z;
   const float n = fmaf(ez, ez, fmaf(ey, ey, ex * ex));
   const float den = n + eps;
   const float inv = den > 0.0f ? 1.0f / den : 0.0f;
-  return make_float4(ex, ey, ez, inv);
+  PairK k;
+  k.e = make_float4(ex, ey, ez, 0.0f);
+  k.ei = make_float4(ex * inv, ey * inv, ez * inv, inv);
+  return k;
 }
 
-// Eq. 4 weight on i for the pixel offset d = I_p - L_j, clamped to [0, 1].
-__device__ __forceinline__ float pair_alpha(float dx, float dy, float dz, float4 t) {
-  const float g = fmaf(dz, t.z, fmaf(dy, t.y, dx * t.x));
-  return clamp01(g * t.w);
+// Eq. 4 weight on i for the pixel offset d = I_p - L_j, clamped to [0, 1]
+// (the clamp folds into the last multiply-add).
+__device__ __forceinline__ float pair_alpha(float dx, float dy, float dz, const PairK& t) {
+  return clamp01(fmaf(dz, t.ei.z, fmaf(dy, t.ei.y, dx * t.ei.x)));
 }
 
 // Residual |d - alpha e|^2 computed from the residual itself (no expansion,
 // so no cancellation when the error is small next to |d|).
-__device__ __forceinline__ float pair_err2(float dx, float dy, float dz, float al, float4 t) {
-  const float rx = fmaf(-al, t.x, dx);
-  const float ry = fmaf(-al, t.y, dy);
-  const float rz = fmaf(-al, t.z, dz);
+__device__ __forceinline__ float pair_err2(float dx, float dy, float dz, float al, const PairK& t) {
+  const float rx = fmaf(-al, t.e.x, dx);
+  const float ry = fmaf(-al, t.e.y, dy);
+  const float rz = fmaf(-al, t.e.z, dz);
   return fmaf(rz, rz, fmaf(ry, ry, rx * rx));
 }
 
@@ -249,7 +259,7 @@ __device__ __forceinline__ void pair_from_index(int p, int& i, int& j) {
 // valid candidate.
 template <int KW, int P, bool BORDER, bool TABLE, typename Win>
 __device__ __forceinline__ void exh_strip(const float (&ip)[P][3], const Win& win,
-                                          const float4* __restrict__ tab, float eps, int kw_rt,
+                                          const PairK* __restrict__ tab, float eps, int kw_rt,
                                           float (&best)[P], int (&code)[P]) {
   constexpr int kUnrollJ = KW == 3 ? 9 : 1;
   constexpr int kUnrollI = KW == 3 ? 8 : 2;
@@ -281,7 +291,7 @@ __device__ __forceinline__ void exh_strip(const float (&ip)[P][3], const Win& wi
     }
 #pragma unroll kUnrollI
     for (int i = 0; i < j; ++i) {
-      float4 t;
+      PairK t;
       if (TABLE) {
         t = tab[pair_index(i, j)];
       } else {
@@ -312,25 +322,92 @@ __device__ __forceinline__ void exh_strip(const float (&ip)[P][3], const Win& wi
   }
 }
 
+// Compile-time loop: f(std::integral_constant<int, I>) for I in [B, E).
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
+}
+
+constexpr int colex_j(int p) {
+  int j = 1;
+  while ((j + 1) * j / 2 <= p) ++j;
+  return j;
+}
+constexpr int colex_i(int p) { return p - colex_j(p) * (colex_j(p) - 1) / 2; }
+
+// Exhaustive search of one strip for a full (interior) 3 x 3 window with the
+// pair table: the 36 pairs are visited in colexicographic order with their
+// indices known at compile time; the table record of the next pair is read
+// from LDS while the current one is evaluated, and a scheduling barrier per
+// pair keeps only two records live (instead of all 36).
+template <int P, typename Win>
+__device__ __forceinline__ void exh_interior3(const float (&ip)[P][3], const Win& win,
+                                              const PairK* __restrict__ tab, float (&best)[P], int (&code)[P]) {
+  constexpr int K2 = 9;
+  constexpr int NP = 36;
+  {
+    const float4 L0 = win(0);
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+      const float dx = ip[q][0] - L0.x, dy = ip[q][1] - L0.y, dz = ip[q][2] - L0.z;
+      best[q] = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+      code[q] = 0;
+    }
+  }
+  float d[P][3];
+  PairK nxt = tab[0];
+  float4 Ln = win(1);
+  static_for<0, NP>([&](auto pc) {
+    constexpr int p = decltype(pc)::value;
+    constexpr int j = colex_j(p), i = colex_i(p);
+    const PairK t = nxt;
+    if constexpr (p + 1 < NP) nxt = tab[p + 1];
+    if constexpr (i == 0) {
+      const float4 Lj = Ln;
+      if constexpr (j + 1 < K2) Ln = win(j + 1);
+#pragma unroll
+      for (int q = 0; q < P; ++q) {
+        d[q][0] = ip[q][0] - Lj.x;
+        d[q][1] = ip[q][1] - Lj.y;
+        d[q][2] = ip[q][2] - Lj.z;
+      }
+    }
+    constexpr int cc = i * K2 + j;
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+      const float al = pair_alpha(d[q][0], d[q][1], d[q][2], t);
+      const float e2 = pair_err2(d[q][0], d[q][1], d[q][2], al, t);
+      const bool lt = e2 < best[q];
+      best[q] = lt ? e2 : best[q];
+      code[q] = lt ? cc : code[q];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  });
+}
+
 // Weight of the winning exhaustive pair, recomputed with the same arithmetic
 // the loop used.
 template <int KW, bool TABLE, typename Win>
 __device__ __forceinline__ float exh_alpha(const float (&ip)[3], const Win& win,
-                                           const float4* __restrict__ tab, float eps, int kw_rt, int code) {
+                                           const PairK* __restrict__ tab, float eps, int kw_rt, int code) {
   const int kw = KW > 0 ? KW : kw_rt;
   const int K2 = kw * kw;
   const int oi = code / K2, oj = code - oi * K2;
-  if (oi == oj) return 1.0f;
   const float4 Lj = win(oj);
-  float4 t;
+  PairK t;
   if (TABLE) {
+    // (oi, oi) maps to a valid table slot (the record after the last pair
+    // of column oi); its value is not used
     t = tab[pair_index(oi, oj)];
   } else {
     const float4 Li = win(oi);
     t = pair_consts(Li, Lj, eps);
   }
-  if (t.w == 0.0f) return 1.0f;
-  return pair_alpha(ip[0] - Lj.x, ip[1] - Lj.y, ip[2] - Lj.z, t);
+  const float al = pair_alpha(ip[0] - Lj.x, ip[1] - Lj.y, ip[2] - Lj.z, t);
+  return (oi == oj || t.ei.w == 0.0f) ? 1.0f : al;
 }
 
 // ---------------------------------------------------------------------------
@@ -428,7 +505,7 @@ __host__ __device__ inline int search_tile_words(int tqy, int tqx, int k, int mo
   const int r = k / 2;
   const int ncell = (tqy + 2 * r) * (tqx + 2 * r);
   int words = ncell * (fused ? 2 : 1);
-  if (mode == MODE_EXH && table) words += tqy * tqx * (n_pairs(k * k) + 1);
+  if (mode == MODE_EXH && table) words += 2 * tqy * tqx * (n_pairs(k * k) + 1);
   return words;
 }
 
@@ -471,8 +548,30 @@ __device__ __forceinline__ void search_tile(const ImgDesc& d, int ty, int tx, fl
   const int ncell = ly * lx;
   float4* sL = smem;
   float4* sT = FUSED ? smem + ncell : nullptr;
-  float4* sTab = smem + (FUSED ? 2 : 1) * ncell;
+  PairK* sTab = reinterpret_cast<PairK*>(smem + (FUSED ? 2 : 1) * ncell);
   const int tstride = n_pairs(K2) + 1;
+
+  const int rows = tqy * s, cols = tqx * s;
+  const int spr = cols / P;
+  const int nstrips = rows * spr;
+  const bool interior = (qy0 - R >= 0) && (qy0 + tqy + R <= d.h) && (qx0 - R >= 0) &&
+                        (qx0 + tqx + R <= d.w) && ((qy0 + tqy) * s <= d.H) && ((qx0 + tqx) * s <= d.W);
+  const bool vecI = (d.vec & VEC_I) != 0, vecTh = (d.vec & VEC_THETA) != 0, vecT = (d.vec & VEC_T) != 0;
+  const T* __restrict__ Ig = static_cast<const T*>(d.I);
+
+  // The HR pixels of a thread's next strip are loaded one strip ahead: the
+  // first strip's loads are in flight while the tile is staged, later ones
+  // while the current strip is searched.
+  float ipn[P][3];
+  auto prefetch = [&](int t) {
+    if (t >= nstrips) return;
+    const int ry = t / spr;
+    const int rx = (t - ry * spr) * P;
+    const int y = qy0 * s + ry, x = qx0 * s + rx;
+    if (y >= d.H || x >= d.W) return;
+    load_strip3<T, P>(Ig + (int64_t)y * d.I_stride, x, d.W, vecI, interior || (x + P <= d.W), ipn);
+  };
+  prefetch(threadIdx.x);
 
   stage_lr<T>(d, qy0, qx0, R, ly, lx, sL, sT);
   __syncthreads();
@@ -491,31 +590,29 @@ __device__ __forceinline__ void search_tile(const ImgDesc& d, int ty, int tx, fl
     __syncthreads();
   }
 
-  const int rows = tqy * s, cols = tqx * s;
-  const int spr = cols / P;
-  const int nstrips = rows * spr;
-  const bool interior = (qy0 - R >= 0) && (qy0 + tqy + R <= d.h) && (qx0 - R >= 0) &&
-                        (qx0 + tqx + R <= d.w) && ((qy0 + tqy) * s <= d.H) && ((qx0 + tqx) * s <= d.W);
-  const bool vecI = (d.vec & VEC_I) != 0, vecTh = (d.vec & VEC_THETA) != 0, vecT = (d.vec & VEC_T) != 0;
-  const T* __restrict__ Ig = static_cast<const T*>(d.I);
-
   for (int t = threadIdx.x; t < nstrips; t += kThreads) {
     const int ry = t / spr;
     const int rx = (t - ry * spr) * P;
     const int y = qy0 * s + ry, x = qx0 * s + rx;
+    float ip[P][3];
+#pragma unroll
+    for (int q = 0; q < P; ++q)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) ip[q][c] = ipn[q][c];
+    prefetch(t + kThreads);
     if (y >= d.H || x >= d.W) continue;
     const int cy = ry / s, cx = rx / s;
     const LdsWin<KW> win{sL + cy * lx + cx, lx, kw};
-    const float4* tab = sTab + (cy * tqx + cx) * tstride;
+    const PairK* tab = sTab + (cy * tqx + cx) * tstride;
     const bool full = interior || (x + P <= d.W);
-
-    float ip[P][3];
-    load_strip3<T, P>(Ig + (int64_t)y * d.I_stride, x, d.W, vecI, full, ip);
     float best[P], al[P];
     int code[P];
     if (MODE == MODE_EXH) {
       if (interior) {
-        exh_strip<KW, P, false, TABLE>(ip, win, tab, eps, kw, best, code);
+        if constexpr (KW == 3 && TABLE)
+          exh_interior3<P>(ip, win, tab, best, code);
+        else
+          exh_strip<KW, P, false, TABLE>(ip, win, tab, eps, kw, best, code);
 #pragma unroll
         for (int q = 0; q < P; ++q) al[q] = exh_alpha<KW, TABLE>(ip[q], win, tab, eps, kw, code[q]);
       } else {
