@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <numeric>
 #include <string>
 
 #include "glu_device.h"
@@ -132,15 +133,22 @@ __global__ __launch_bounds__(kThreads) void k_search(const ImgDesc d, float eps)
   search_tile<KW, P, MODE, T, FUSED, (MODE == MODE_EXH && KW > 0)>(d, ty, tx, eps, smem);
 }
 
-// One workgroup per run of kThreads * kApplyStrips strips of one HR row.
+// One workgroup per tile of one LR row by d.tqx LR columns.
 template <int KW, int P, typename T>
-__global__ __launch_bounds__(kThreads) void k_apply(const ImgDesc d, int runs, uint32_t s_magic) {
-  const int y = blockIdx.x / runs, run = blockIdx.x - y * runs;
-  apply_row_run<KW, P, T, kApplyStrips>(d, y, run, s_magic);
+__global__ __launch_bounds__(kThreads) void k_apply(const ImgDesc d, uint32_t s_magic) {
+  extern __shared__ float4 smem[];
+  const int tile = blockIdx.x;
+  const int qy = tile / d.tiles_x, qx0 = (tile - qy * d.tiles_x) * d.tqx;
+  switch (d.C) {
+    case 1: apply_tile<KW, P, T, 1, kApplyStrips>(d, qy, qx0, s_magic, smem); break;
+    case 2: apply_tile<KW, P, T, 2, kApplyStrips>(d, qy, qx0, s_magic, smem); break;
+    case 3: apply_tile<KW, P, T, 3, kApplyStrips>(d, qy, qx0, s_magic, smem); break;
+    default: apply_tile<KW, P, T, 4, kApplyStrips>(d, qy, qx0, s_magic, smem); break;
+  }
 }
 
 typedef void (*SearchKernel)(const ImgDesc, float);
-typedef void (*ApplyKernel)(const ImgDesc, int, uint32_t);
+typedef void (*ApplyKernel)(const ImgDesc, uint32_t);
 
 template <int KW, int P, typename T>
 static SearchKernel pick_search_t(int mode, bool fused) {
@@ -190,6 +198,18 @@ uint32_t launch_vec_flags(const ImgDesc& d, int P, size_t esize) {
   if (th) v |= VEC_THETA;
   if (d.That && (d.C == 3 || d.C == 1) && aligned(d.That, va) && d.That_stride % 4 == 0) v |= VEC_T;
   return v;
+}
+
+// Apply tile width in LR columns: a multiple of the smallest width whose
+// HR span tqx * s is a multiple of 64 * P (so every wave run lies in one HR
+// row and starts 64-pixel aligned), near 1024 strips per tile, and shrunk
+// while the tile's LDS exceeds 24 KiB.
+int apply_tile_width(int s, int P, int k, int C, int esize) {
+  const int span = 64 * P;
+  int unit = span / std::gcd(s, span);
+  int tqx = std::max(1, (1024 * P / (s * s)) / unit) * unit;
+  while (tqx > unit && 16 * apply_tile_words(tqx, k, P, C, esize) > 24 * 1024) tqx -= unit;
+  return tqx;
 }
 
 // Validates and launches search (fused when T/That given).
@@ -371,13 +391,19 @@ glu_status glu_apply(const glu_theta* theta, const glu_image* T_low, const glu_p
   d.C = T_low->channels;
   d.dtype = T_low->dtype;
   const int P = (p->s % 4 == 0) ? 4 : 1;
-  d.vec = launch_vec_flags(d, P, dtype_size(T_low->dtype));
-  const int runs = ceil_div(W, P * kThreads * kApplyStrips);
-  const int64_t groups = (int64_t)runs * H;
+  const int es = (int)dtype_size(T_low->dtype);
+  d.vec = launch_vec_flags(d, P, es);
+  if (aligned(T_hat->data, 16) && (T_hat->row_stride * es) % 16 == 0) d.vec |= VEC_TW;
+  d.tqx = apply_tile_width(p->s, P, p->k, d.C, es);
+  d.tqy = 1;
+  d.tiles_x = ceil_div(w, d.tqx);
+  d.tiles_y = h;
+  const int64_t groups = (int64_t)d.tiles_x * h;
   if (groups > 0x7fffffff) return fail(GLU_ERR_UNSUPPORTED, "image too large");
   const uint32_t s_magic = (uint32_t)std::min<uint64_t>(0xffffffffull, (1ull << 32) / (uint64_t)p->s);
+  const size_t lds = 16 * (size_t)apply_tile_words(d.tqx, p->k, P, d.C, es);
   ApplyKernel kern = pick_apply(p->k, P, T_low->dtype);
-  hipLaunchKernelGGL(kern, dim3((unsigned)groups), dim3(kThreads), 0, (hipStream_t)stream, d, runs, s_magic);
+  hipLaunchKernelGGL(kern, dim3((unsigned)groups), dim3(kThreads), lds, (hipStream_t)stream, d, s_magic);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "apply launch");
   return GLU_OK;

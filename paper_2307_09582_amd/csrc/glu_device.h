@@ -650,13 +650,16 @@ __device__ __forceinline__ void search_tile(const ImgDesc& d, int ty, int tx, fl
 }
 
 // ---------------------------------------------------------------------------
-// Apply (Eq. 1) over runs of one HR row
+// Apply (Eq. 1) over tiles of one LR row
 // ---------------------------------------------------------------------------
-// Apply is a pure stream (6 bytes of Theta in, 4C bytes out per pixel).  A
-// workgroup owns a run of kThreads * NS strips of P pixels of one HR row, so
-// its loads and stores are contiguous; the two LR cells of a pixel are
-// gathered straight from global memory (the LR target is small and stays
-// in the caches).  No LDS, no barrier.
+// Apply is a pure stream: 6 bytes of Theta in and C * sizeof(T) bytes of
+// T_hat out per pixel.  A workgroup owns the s HR rows of one LR row over
+// tqx LR columns.  It issues the Theta loads of its first strips, stages
+// the k rows of LR target cells the tile can reach in LDS (one float4 per
+// cell), and gathers from LDS.  tqx * s is a multiple of 64 * P, so the 64
+// strips of a wave are consecutive pixels of one HR row: the wave writes
+// its results to an LDS buffer and stores them as one contiguous run of
+// 16-byte words (non-temporal, the output is not read again here).
 //
 // Unsigned division by a runtime divisor d < 2^16 for n < 2^31: the estimate
 // q = umulhi(n, floor(2^32 / d)) is floor(n / d) or one less; one
@@ -676,81 +679,169 @@ __device__ __forceinline__ float4 load_cell(const T* __restrict__ p, int C) {
   return make_float4(v[0], v[1], v[2], v[3]);
 }
 
-template <int KW, int P, typename T, int NS>
-__device__ __forceinline__ void apply_row_run(const ImgDesc& d, int y, int run, uint32_t s_magic) {
+// Writes N values of T to LDS at dst (aligned to the widest power of two,
+// up to 16, that divides N * sizeof(T)) with the widest such accesses.
+template <typename T, int N>
+__device__ __forceinline__ void lds_put(char* dst, const T (&v)[N]) {
+  constexpr int B = N * (int)sizeof(T);
+  if constexpr (B % 16 == 0) {
+    uint4 w[B / 16];
+    __builtin_memcpy(w, v, B);
+#pragma unroll
+    for (int i = 0; i < B / 16; ++i) reinterpret_cast<uint4*>(dst)[i] = w[i];
+  } else if constexpr (B % 8 == 0) {
+    uint2 w[B / 8];
+    __builtin_memcpy(w, v, B);
+#pragma unroll
+    for (int i = 0; i < B / 8; ++i) reinterpret_cast<uint2*>(dst)[i] = w[i];
+  } else if constexpr (B % 4 == 0) {
+    uint32_t w[B / 4];
+    __builtin_memcpy(w, v, B);
+#pragma unroll
+    for (int i = 0; i < B / 4; ++i) reinterpret_cast<uint32_t*>(dst)[i] = w[i];
+  } else {
+    uint16_t w[B / 2];
+    __builtin_memcpy(w, v, B);
+#pragma unroll
+    for (int i = 0; i < B / 2; ++i) reinterpret_cast<uint16_t*>(dst)[i] = w[i];
+  }
+}
+
+// LDS float4 words of one apply tile: the staged LR cells plus one output
+// buffer per wave.
+__host__ __device__ inline int apply_tile_words(int tqx, int k, int P, int C, int esize) {
+  return k * (tqx + k - 1) + (kThreads / 64) * 4 * P * C * esize;
+}
+
+template <int KW, int P, typename T, int C, int NS>
+__device__ __forceinline__ void apply_tile(const ImgDesc& d, int qy, int qx0, uint32_t s_magic, float4* smem) {
+  constexpr int B = P * C * (int)sizeof(T);  // bytes of one strip of T_hat
+  constexpr int kWords = 4 * B;              // 16-byte words of a wave's 64 strips
+  constexpr int kWaves = kThreads / 64;
   const int kw = KW > 0 ? KW : d.k;
   const int R = kw / 2;
   const int K2 = kw * kw;
   const int maxcode = K2 * K2 - 1;
-  const int s = d.s, C = d.C;
-  const bool vecTh = (d.vec & VEC_THETA) != 0, vecT = (d.vec & VEC_T) != 0;
-  const int qy = udiv_rt(y, s, s_magic);
+  const int s = d.s, tqx = d.tqx, lx = tqx + kw - 1;
+  const int wave = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
+  const int wpr = tqx * s / (64 * P);  // wave runs per HR row
+  const int nrun = s * wpr;             // wave runs of the tile
+  const int xt = qx0 * s;               // first HR column of the tile
+  float4* sT = smem;
+  char* sx = reinterpret_cast<char*>(smem + kw * lx) + wave * kWords * 16;
+  const bool vecTh = P == 4 && (d.vec & VEC_THETA) != 0;
+  const bool vecTW = (d.vec & VEC_TW) != 0;
   const T* __restrict__ TL = static_cast<const T*>(d.T);
-  const int64_t trow = (int64_t)y * d.th_stride;
-  int code[NS][P];
+
+  int cd[NS][P];
   float al[NS][P];
-  int xs[NS];
+  int ys[NS], x0s[NS];
+  // Theta of the strips of wave runs g0 + n * kWaves + wave, n < NS
+  auto load = [&](int g0) {
 #pragma unroll
-  for (int n = 0; n < NS; ++n) {
-    const int x = ((run * NS + n) * kThreads + (int)threadIdx.x) * P;
-    xs[n] = x;
-    const bool live = x < d.W;
-    const bool full = x + P <= d.W;
-    const int64_t to = trow + x;
-    bool done = false;
-    if constexpr (P == 4) {
-      if (live && full && vecTh) {
-        const u32x2 c = __builtin_nontemporal_load(reinterpret_cast<const u32x2*>(d.code + to));
-        const f32x4 a4 = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(d.alpha + to));
-        code[n][0] = c.x & 0xffff;
-        code[n][1] = c.x >> 16;
-        code[n][2] = c.y & 0xffff;
-        code[n][3] = c.y >> 16;
-        al[n][0] = a4.x;
-        al[n][1] = a4.y;
-        al[n][2] = a4.z;
-        al[n][3] = a4.w;
-        done = true;
+    for (int n = 0; n < NS; ++n) {
+      const int g = g0 + n * kWaves + wave;  // uniform over the wave
+      const int row = g / wpr;
+      const int y = qy * s + row;
+      const int x0 = xt + (g - row * wpr) * 64 * P;
+      const int x = x0 + lane * P;
+      ys[n] = (g < nrun && y < d.H) ? y : -1;
+      x0s[n] = x0;
+      const bool live = ys[n] >= 0 && x < d.W;
+      const int64_t to = (int64_t)y * d.th_stride + x;
+      bool done = false;
+      if constexpr (P == 4) {
+        if (live && vecTh && x + P <= d.W) {
+          const u32x2 c = __builtin_nontemporal_load(reinterpret_cast<const u32x2*>(d.code + to));
+          const f32x4 a4 = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(d.alpha + to));
+          cd[n][0] = c.x & 0xffff;
+          cd[n][1] = c.x >> 16;
+          cd[n][2] = c.y & 0xffff;
+          cd[n][3] = c.y >> 16;
+          al[n][0] = a4.x;
+          al[n][1] = a4.y;
+          al[n][2] = a4.z;
+          al[n][3] = a4.w;
+          done = true;
+        }
+      }
+      if (!done) {
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+          const bool ok = live && x + q < d.W;
+          cd[n][q] = ok ? (int)d.code[to + q] : 0;
+          al[n][q] = ok ? d.alpha[to + q] : 0.0f;
+        }
       }
     }
-    if (!done) {
+  };
+
+  load(0);
+  // LR target cells rows qy - R .. qy + R, columns qx0 - R .. qx0 + tqx - 1 + R,
+  // clamped to the LR image (codes from the search never leave it; other
+  // codes read the nearest cell instead of leaving the buffer)
+  for (int i = (int)threadIdx.x; i < kw * lx; i += kThreads) {
+    const int r = i / lx, c = i - r * lx;
+    const int cy = min(max(qy - R + r, 0), d.h - 1);
+    const int cx = min(max(qx0 - R + c, 0), d.w - 1);
+    sT[i] = load_cell<T>(TL + (int64_t)cy * d.T_stride + (int64_t)cx * C, C);
+  }
+  __syncthreads();
+
+  for (int g0 = 0;;) {
+#pragma unroll
+    for (int n = 0; n < NS; ++n) {
+      const int y = ys[n];
+      if (y < 0) continue;  // uniform over the wave
+      const int x0 = x0s[n];
+      const int x = x0 + lane * P;
+      // all P pixels of a strip share their LR cell (P divides s); cells
+      // of lanes past the right edge stay inside the tile
+      const int cx = udiv_rt(x - xt, s, s_magic);
+      float o[P][C];
 #pragma unroll
       for (int q = 0; q < P; ++q) {
-        const bool ok = x + q < d.W;
-        code[n][q] = ok ? d.code[to + q] : 0;
-        al[n][q] = ok ? d.alpha[to + q] : 0.0f;
+        const int c = min(cd[n][q], maxcode);
+        const int oa = c / K2, ob = c - oa * K2;
+        const float4 ta = sT[(oa / kw) * lx + cx + oa % kw];
+        const float4 tb = sT[(ob / kw) * lx + cx + ob % kw];
+        const float va[4] = {ta.x, ta.y, ta.z, ta.w};
+        const float vb[4] = {tb.x, tb.y, tb.z, tb.w};
+#pragma unroll
+        for (int ch = 0; ch < C; ++ch) o[q][ch] = fmaf(al[n][q], va[ch] - vb[ch], vb[ch]);
+      }
+      T* __restrict__ orow = static_cast<T*>(d.That) + (int64_t)y * d.That_stride;
+      if (vecTW && x0 + 64 * P <= d.W) {
+        T v[P * C];
+#pragma unroll
+        for (int q = 0; q < P; ++q)
+#pragma unroll
+          for (int ch = 0; ch < C; ++ch) v[q * C + ch] = from_f<T>(o[q][ch]);
+        lds_put<T, P * C>(sx + lane * B, v);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        f32x4* dst = reinterpret_cast<f32x4*>(orow + (int64_t)x0 * C);
+        const f32x4* src = reinterpret_cast<const f32x4*>(sx);
+#pragma unroll
+        for (int k16 = 0; k16 < (kWords + 63) / 64; ++k16) {
+          const int idx = lane + 64 * k16;
+          if (idx < kWords) __builtin_nontemporal_store(src[idx], dst + idx);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      } else {
+#pragma unroll
+        for (int q = 0; q < P; ++q)
+          if (x + q < d.W)
+#pragma unroll
+            for (int ch = 0; ch < C; ++ch) orow[(int64_t)(x + q) * C + ch] = from_f<T>(o[q][ch]);
       }
     }
-  }
-#pragma unroll
-  for (int n = 0; n < NS; ++n) {
-    const int x = xs[n];
-    if (x >= d.W) continue;
-    const bool full = x + P <= d.W;
-    // all P pixels of a strip share their LR cell (P divides s)
-    const int qx = udiv_rt(x, s, s_magic);
-    float o[P][4];
-#pragma unroll
-    for (int q = 0; q < P; ++q) {
-      const int cd = min(code[n][q], maxcode);
-      const int oa = cd / K2, ob = cd - oa * K2;
-      const int ay = qy + oa / kw - R, ax = qx + oa % kw - R;
-      const int by = qy + ob / kw - R, bx = qx + ob % kw - R;
-      float4 Ta = make_float4(0.f, 0.f, 0.f, 0.f), Tb = Ta;
-      if (x + q < d.W) {
-        // codes from the search always point inside the LR image; others
-        // are clamped so that the gather stays inside the buffer
-        const int ayc = min(max(ay, 0), d.h - 1), axc = min(max(ax, 0), d.w - 1);
-        const int byc = min(max(by, 0), d.h - 1), bxc = min(max(bx, 0), d.w - 1);
-        Ta = load_cell<T>(TL + (int64_t)ayc * d.T_stride + (int64_t)axc * C, C);
-        Tb = load_cell<T>(TL + (int64_t)byc * d.T_stride + (int64_t)bxc * C, C);
-      }
-      o[q][0] = fmaf(al[n][q], Ta.x - Tb.x, Tb.x);
-      o[q][1] = fmaf(al[n][q], Ta.y - Tb.y, Tb.y);
-      o[q][2] = fmaf(al[n][q], Ta.z - Tb.z, Tb.z);
-      o[q][3] = fmaf(al[n][q], Ta.w - Tb.w, Tb.w);
-    }
-    store_out<T, P>(static_cast<T*>(d.That) + (int64_t)y * d.That_stride, x, d.W, C, vecT, full, o);
+    g0 += NS * kWaves;
+    if (g0 >= nrun) break;
+    load(g0);
   }
 }
 

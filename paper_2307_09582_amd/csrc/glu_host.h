@@ -52,6 +52,9 @@ int kernel_variant(int k, int P, int mode, int dtype);
 // VEC_* alignment flags of a launch (vector loads / stores allowed).
 uint32_t launch_vec_flags(const ImgDesc& d, int P, size_t esize);
 
+// Apply tile width in LR columns (see apply_tile).
+int apply_tile_width(int s, int P, int k, int C, int esize);
+
 // Tile variant recorded by the autotuner for (mode, k, s, dtype), 0 if none.
 int tuned_variant(int mode, int k, int s, int dtype);
 

@@ -14,7 +14,7 @@ namespace glu {
 constexpr int kThreads = 256;       // threads per workgroup (4 wave64)
 constexpr int kMaxK = 15;           // largest window (code fits uint16)
 constexpr int kLdsBudget = 60 * 1024;  // dynamic LDS per workgroup we allow
-constexpr int kApplyStrips = 4;     // strips per thread in the apply kernel
+constexpr int kApplyStrips = 4;     // strips per thread and pass in the apply kernel
 
 // Alignment flags of one launch (all pixels of a launch share them).
 enum : uint32_t {
@@ -22,6 +22,8 @@ enum : uint32_t {
   VEC_THETA = 1u << 1,  // theta / err rows allow vector stores
   VEC_T = 1u << 2,      // T_hat rows allow vector stores (C == 1 or 3)
   VEC_G = 1u << 3,      // gradient rows allow vector loads
+  VEC_TW = 1u << 4,     // T_hat base and rows 16-byte aligned (apply stores a
+                        // wave's 64 strips as one run of 16-byte words)
 };
 
 // One image of a search / apply launch.  The plain entry points launch one

@@ -94,6 +94,10 @@ CASES = [
     (57, 61, 4, 3, 1, "exhaustive", "f16"),
     (96, 100, 12, 3, 3, "exhaustive", "f32"),
     (48, 48, 4, 9, 3, "exhaustive", "f32"),
+    (30, 45, 3, 3, 3, "exhaustive", "f16"),
+    (30, 45, 2, 3, 1, "fast", "f16"),
+    (40, 72, 4, 3, 4, "fast", "f16"),
+    (40, 72, 4, 3, 2, "exhaustive", "f16"),
 ]
 
 
@@ -214,3 +218,76 @@ def test_full_4k_x8_sampled(mode):
     rep = check_search(I, L, s, 3, 1e-3, mode, host(th.code), host(th.alpha), err=host(err), pixels=pix,
                        T_low=T, T_hat=host(out))
     print(rep)
+
+
+def _random_theta(H, W, s, k, rng):
+    """Codes of random pairs inside each pixel's border-truncated window and
+    random weights in [0, 1]; returns (code, alpha, a, b) with absolute LR
+    indices a, b."""
+    h, w = -(-H // s), -(-W // s)
+    r = k // 2
+    ys, xs = np.mgrid[0:H, 0:W]
+    qy, qx = ys // s, xs // s
+
+    def offset():
+        lo_y, hi_y = np.maximum(-r, -qy), np.minimum(r, h - 1 - qy)
+        lo_x, hi_x = np.maximum(-r, -qx), np.minimum(r, w - 1 - qx)
+        dy = lo_y + np.floor(rng.random((H, W)) * (hi_y - lo_y + 1)).astype(np.int64)
+        dx = lo_x + np.floor(rng.random((H, W)) * (hi_x - lo_x + 1)).astype(np.int64)
+        return (dy + r) * k + (dx + r), (qy + dy) * w + (qx + dx)
+
+    oa, a = offset()
+    ob, b = offset()
+    code = (oa * k * k + ob).astype(np.uint16).view(np.int16)
+    alpha = rng.random((H, W)).astype(np.float32)
+    alpha[0, 0] = 0.0
+    alpha[-1, -1] = 1.0
+    return code, alpha, a, b
+
+
+APPLY_CASES = [
+    # H, W, s, k, C, dtype, extra row padding (pixels), column offset of the output view
+    (96, 1000, 8, 3, 3, "f32", 0, 0),
+    (64, 520, 8, 3, 3, "f32", 4, 1),
+    (16, 4160, 8, 3, 3, "f32", 4, 0),
+    (70, 300, 4, 5, 4, "f32", 0, 0),
+    (50, 200, 16, 3, 3, "f32", 0, 0),
+    (20, 700, 1, 3, 3, "f32", 0, 0),
+    (25, 77, 5, 7, 3, "f32", 0, 0),
+    (33, 250, 3, 3, 3, "f16", 0, 0),
+    (33, 250, 2, 3, 1, "f16", 0, 0),
+    (40, 130, 4, 3, 2, "f16", 0, 0),
+    (40, 136, 8, 3, 3, "f16", 2, 1),
+    (9, 2100, 12, 3, 1, "f32", 0, 0),
+]
+
+
+@pytest.mark.parametrize("H,W,s,k,C,dt,pad,off", APPLY_CASES)
+def test_apply_random_theta(H, W, s, k, C, dt, pad, off):
+    """glu_apply with random valid Theta against Eq. 1 in float64, into
+    dense outputs and into views whose rows are padded or misaligned."""
+    glu = _glu()
+    log_case(test="apply_random_theta", H=H, W=W, s=s, k=k, C=C, dt=dt, pad=pad, off=off)
+    rng = np.random.default_rng(H * 7919 + W * 31 + s)
+    code, alpha, a, b = _random_theta(H, W, s, k, rng)
+    h, w = -(-H // s), -(-W // s)
+    npd = np.float16 if dt == "f16" else np.float32
+    T = rng.random((h, w, C)).astype(npd)
+    th = glu.Theta(dev(code), dev(alpha))
+    big = torch.full((H, W + pad + off, C), float("nan"), dtype=torch.float16 if dt == "f16" else torch.float32,
+                     device="cuda")
+    view = big[:, off:off + W]
+    out = glu.apply(th, dev(T), s, k, out=view)
+    got = host(out).astype(np.float64)
+    ref = O.apply(a, b, alpha, T)
+    if dt == "f16":
+        tol = np.spacing(np.abs(ref).astype(np.float16)).astype(np.float64) + 1e-5
+    else:
+        tol = 1e-5
+    bad = np.abs(got - ref) > tol
+    assert not bad.any(), "apply mismatch at %d values, first %s" % (int(bad.sum()), np.argwhere(bad)[0])
+    rest = host(big)
+    if off:
+        assert np.isnan(rest[:, :off]).all()
+    if pad:
+        assert np.isnan(rest[:, off + W:]).all()
