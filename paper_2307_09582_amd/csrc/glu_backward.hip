@@ -9,14 +9,17 @@
 // done in two passes over a caller-provided workspace S:
 //
 //   pass 1 (HR stream, one read of G and Theta): for every LR cell c and
-//     every window offset o, S[c][o] = sum over the pixels of c's s x s
+//     every window offset o, S[o][c] = sum over the pixels of c's s x s
 //     block, in raster order, of the part of their contribution aimed at the
 //     cell c + offset(o).  A workgroup owns nb consecutive cells of one LR
-//     row: it streams their s HR rows (vector loads, dL/dalpha written on
-//     the way) into LDS, then one thread per (cell, o) scans the block's
-//     pixels in raster order.
+//     row (nb * k^2 <= 256).  It stages the LR target cells its pixels can
+//     reach in LDS, streams chunks of its HR rows (vector loads; dL/dalpha
+//     computed from the staged cells and written on the way) into LDS, and
+//     then one lane per (cell, offset) scans the chunk's pixels of its cell
+//     in raster order without branches.
 //   pass 2 (LR): dT_low[q] = sum over o in ascending order of
-//     S[q - offset(o)][o].
+//     S[o][q - offset(o)].  S is offset-major, so for each o neighbouring
+//     lanes read neighbouring cells.
 //
 // Both passes use fixed summation orders, so results are bitwise
 // reproducible.
@@ -39,7 +42,7 @@ struct BwdArgs {
   float* dT;            // grad_T_low (C channels), nullable
   int64_t th_stride, T_stride, G_stride, dT_stride;
   int32_t H, W, h, w, s, k, C;
-  int32_t nb;           // LR cells per workgroup (one LR row)
+  int32_t nb;           // LR cells per workgroup (one LR row), nb * k^2 <= 256
   int32_t rows_chunk;   // HR rows staged per chunk
   int32_t groups_x;     // workgroups per LR row
   uint32_t s_magic;     // floor(2^32 / s) for udiv_rt
@@ -52,47 +55,65 @@ template <int P>
 __device__ __forceinline__ void load_grad(const float* __restrict__ row, int x, int W, int C, bool vec, bool full,
                                           float (&g)[P][4]) {
   const float* p = row + (int64_t)x * C;
+  bool done = false;
+  f32x4 v0 = {0.f, 0.f, 0.f, 0.f}, v1 = v0, v2 = v0;
   if constexpr (P == 4) {
     if (vec && full && C == 3) {
-      const float4* q = reinterpret_cast<const float4*>(p);
-      const float4 a = q[0], b = q[1], c = q[2];
-      g[0][0] = a.x; g[0][1] = a.y; g[0][2] = a.z;
-      g[1][0] = a.w; g[1][1] = b.x; g[1][2] = b.y;
-      g[2][0] = b.z; g[2][1] = b.w; g[2][2] = c.x;
-      g[3][0] = c.y; g[3][1] = c.z; g[3][2] = c.w;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) g[i][3] = 0.f;
-      return;
-    }
-    if (vec && full && C == 1) {
-      const float4 a = *reinterpret_cast<const float4*>(p);
-      g[0][0] = a.x; g[1][0] = a.y; g[2][0] = a.z; g[3][0] = a.w;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) g[i][1] = g[i][2] = g[i][3] = 0.f;
-      return;
+      const f32x4* q = reinterpret_cast<const f32x4*>(p);
+      v0 = __builtin_nontemporal_load(q);
+      v1 = __builtin_nontemporal_load(q + 1);
+      v2 = __builtin_nontemporal_load(q + 2);
+      done = true;
+    } else if (vec && full && C == 1) {
+      const f32x4 a = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(p));
+      // spread as C == 3 rows would be, channel 0 only
+      v0 = f32x4{a.x, 0.f, 0.f, a.y};
+      v1 = f32x4{0.f, 0.f, a.z, 0.f};
+      v2 = f32x4{0.f, a.w, 0.f, 0.f};
+      done = true;
     }
   }
+  if (done) {
+    if constexpr (P == 4) {
+      g[0][0] = v0.x; g[0][1] = v0.y; g[0][2] = v0.z;
+      g[1][0] = v0.w; g[1][1] = v1.x; g[1][2] = v1.y;
+      g[2][0] = v1.z; g[2][1] = v1.w; g[2][2] = v2.x;
+      g[3][0] = v2.y; g[3][1] = v2.z; g[3][2] = v2.w;
 #pragma unroll
-  for (int i = 0; i < P; ++i) {
-    const bool ok = full || (x + i < W);
+      for (int i = 0; i < 4; ++i) g[i][3] = 0.f;
+    }
+  } else {
 #pragma unroll
-    for (int c = 0; c < 4; ++c) g[i][c] = (ok && c < C) ? p[i * C + c] : 0.f;
+    for (int i = 0; i < P; ++i) {
+      const bool ok = full || (x + i < W);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) g[i][c] = (ok && c < C) ? p[i * C + c] : 0.f;
+    }
   }
 }
 
-// LDS layout of pass 1 for one chunk of HR rows of the group: per pixel slot
-// a packed code word (o_a | o_b << 8), alpha, and C gradient values (SoA).
-template <typename T, int P>
+// LDS float4 words of pass 1: staged LR target cells, then per pixel slot of
+// a chunk a float4 of gradients, a float alpha and a uint16 code pair.
+__host__ __device__ inline int bwd_lds_words(int k, int nb, int s, int rows_chunk) {
+  const int n = rows_chunk * nb * s;
+  return k * (nb + k - 1) + n + (n + 3) / 4 + (n + 7) / 8;
+}
+
+template <typename T, int P, int KW>
 __global__ __launch_bounds__(kThreads) void k_bwd_block(const BwdArgs a) {
   extern __shared__ float4 smem[];
-  const int k = a.k, r = k / 2, K2 = k * k, s = a.s, C = a.C;
+  const int k = KW > 0 ? KW : a.k;
+  const int r = k / 2, K2 = k * k, s = a.s, C = a.C;
   const int qy = blockIdx.x / a.groups_x;
   const int qx0 = (blockIdx.x - qy * a.groups_x) * a.nb;
   const int nb = min(a.nb, a.w - qx0);
-  const int chunk_px = a.rows_chunk * a.nb * s;  // pixel slots per chunk
-  int* sCode = reinterpret_cast<int*>(smem);
-  float* sAl = reinterpret_cast<float*>(sCode + chunk_px);
-  float* sG = sAl + chunk_px;  // C * chunk_px
+  const int pitch = a.nb * s;                  // slots per staged HR row
+  const int nslot = a.rows_chunk * pitch;
+  const int lx = a.nb + k - 1;
+  float4* sT = smem;
+  float4* sG = smem + k * lx;
+  float* sA = reinterpret_cast<float*>(sG + nslot);
+  uint16_t* sC = reinterpret_cast<uint16_t*>(sA + ((nslot + 3) & ~3));
   const T* __restrict__ TL = static_cast<const T*>(a.T);
   const bool vecTh = (a.vec & VEC_THETA) != 0, vecG = (a.vec & VEC_G) != 0, vecA = (a.vec & VEC_T) != 0;
 
@@ -100,17 +121,30 @@ __global__ __launch_bounds__(kThreads) void k_bwd_block(const BwdArgs a) {
   const int x0 = qx0 * s, x1 = min(a.W, x0 + nb * s);
   const int seg = x1 - x0;             // pixels per HR row of the group
   const int spr = (seg + P - 1) / P;   // strips per HR row of the group
-  const int n_pairs_grp = nb * K2;
-  float acc[2][4];
-#pragma unroll
-  for (int u = 0; u < 2; ++u)
-#pragma unroll
-    for (int ch = 0; ch < 4; ++ch) acc[u][ch] = 0.f;
+
+  if (a.dalpha) {
+    // LR target cells rows qy - r .. qy + r, columns qx0 - r .. qx0 + a.nb - 1 + r,
+    // clamped to the LR image (codes from the search never leave it)
+    for (int i = (int)threadIdx.x; i < k * lx; i += kThreads) {
+      const int rr = i / lx, c = i - rr * lx;
+      const int cy = min(max(qy - r + rr, 0), a.h - 1);
+      const int cx = min(max(qx0 - r + c, 0), a.w - 1);
+      sT[i] = load_cell<T>(TL + (int64_t)cy * a.T_stride + (int64_t)cx * C, C);
+    }
+    __syncthreads();
+  }
+
+  // scan lane: one (cell, offset) pair of the group
+  const int lane_cell = (int)threadIdx.x / K2;
+  const int lane_o = (int)threadIdx.x - lane_cell * K2;
+  const bool scanner = a.S && lane_cell < nb;
+  const int cx0 = lane_cell * s, cx1 = min(seg, cx0 + s);  // pixel columns of the cell
+  float acc[4] = {0.f, 0.f, 0.f, 0.f};
 
   for (int yc = y0; yc < y1; yc += a.rows_chunk) {
-    const int yce = min(y1, yc + a.rows_chunk);
-    const int nstrips = (yce - yc) * spr;
-    for (int t = threadIdx.x; t < nstrips; t += kThreads) {
+    const int nrow = min(y1, yc + a.rows_chunk) - yc;
+    const int nstrips = nrow * spr;
+    for (int t = (int)threadIdx.x; t < nstrips; t += kThreads) {
       const int ry = t / spr;
       const int rx = (t - ry * spr) * P;
       const int y = yc + ry, x = x0 + rx;
@@ -144,30 +178,27 @@ __global__ __launch_bounds__(kThreads) void k_bwd_block(const BwdArgs a) {
       }
       float g[P][4];
       load_grad<P>(a.G + (int64_t)y * a.G_stride, x, a.W, C, vecG, full, g);
-      const int qx = udiv_rt(x, s, a.s_magic);  // all P pixels share it
+      // cell of the strip inside the group (all P pixels share it)
+      const int cl = udiv_rt(rx, s, a.s_magic);
       float da[P];
 #pragma unroll
       for (int q = 0; q < P; ++q) {
         const int cdc = min(cd[q], K2 * K2 - 1);
         const int oa = cdc / K2, ob = cdc - oa * K2;
-        const int i = ry * seg + rx + q;
-        if (full || rx + q < seg) {
-          sCode[i] = oa | (ob << 8);
-          sAl[i] = al[q];
-#pragma unroll
-          for (int ch = 0; ch < 4; ++ch)
-            if (ch < C) sG[ch * chunk_px + i] = g[q][ch];
+        const int i = ry * pitch + rx + q;
+        if (a.S && (full || rx + q < seg)) {
+          sG[i] = make_float4(g[q][0], g[q][1], g[q][2], g[q][3]);
+          sA[i] = al[q];
+          sC[i] = (uint16_t)(oa | (ob << 8));
         }
         da[q] = 0.f;
-        if (a.dalpha && (full || rx + q < seg)) {
-          const int ay = min(max(qy + oa / k - r, 0), a.h - 1), ax = min(max(qx + oa % k - r, 0), a.w - 1);
-          const int by = min(max(qy + ob / k - r, 0), a.h - 1), bx = min(max(qx + ob % k - r, 0), a.w - 1);
-          const float4 Ta = load_cell<T>(TL + (int64_t)ay * a.T_stride + (int64_t)ax * C, C);
-          const float4 Tb = load_cell<T>(TL + (int64_t)by * a.T_stride + (int64_t)bx * C, C);
+        if (a.dalpha) {
+          const float4 Ta = sT[(oa / k) * lx + cl + oa % k];
+          const float4 Tb = sT[(ob / k) * lx + cl + ob % k];
           float v = g[q][0] * (Ta.x - Tb.x);
-          if (C > 1) v = fmaf(g[q][1], Ta.y - Tb.y, v);
-          if (C > 2) v = fmaf(g[q][2], Ta.z - Tb.z, v);
-          if (C > 3) v = fmaf(g[q][3], Ta.w - Tb.w, v);
+          v = fmaf(g[q][1], Ta.y - Tb.y, v);
+          v = fmaf(g[q][2], Ta.z - Tb.z, v);
+          v = fmaf(g[q][3], Ta.w - Tb.w, v);
           da[q] = v;
         }
       }
@@ -175,7 +206,8 @@ __global__ __launch_bounds__(kThreads) void k_bwd_block(const BwdArgs a) {
         bool st = false;
         if constexpr (P == 4) {
           if (vecA && full) {
-            *reinterpret_cast<float4*>(a.dalpha + to) = make_float4(da[0], da[1], da[2], da[3]);
+            __builtin_nontemporal_store(f32x4{da[0], da[1], da[2], da[3]},
+                                        reinterpret_cast<f32x4*>(a.dalpha + to));
             st = true;
           }
         }
@@ -186,51 +218,44 @@ __global__ __launch_bounds__(kThreads) void k_bwd_block(const BwdArgs a) {
         }
       }
     }
+    if (!a.S) continue;
     __syncthreads();
-    if (a.S) {
-      // each thread owns up to two (cell, offset) pairs of the group
-#pragma unroll
-      for (int u = 0; u < 2; ++u) {
-        const int pr = threadIdx.x + u * kThreads;
-        if (pr >= n_pairs_grp) continue;
-        const int cell = pr / K2, o = pr - cell * K2;
-        const int cx0 = cell * s, cx1 = min(seg, cx0 + s);  // pixel columns of this cell
-        for (int ry = 0; ry < yce - yc; ++ry) {
-          for (int rx = cx0; rx < cx1; ++rx) {
-            const int i = ry * seg + rx;
-            const int pk = sCode[i];
-            const int oa = pk & 0xff, ob = pk >> 8;
-            if (oa == o || ob == o) {
-              const float al = sAl[i];
-              float wgt = (oa == o) ? al : 0.0f;
-              wgt = (ob == o) ? wgt + (1.0f - al) : wgt;
-#pragma unroll
-              for (int ch = 0; ch < 4; ++ch)
-                if (ch < C) acc[u][ch] = fmaf(wgt, sG[ch * chunk_px + i], acc[u][ch]);
-            }
-          }
+    if (scanner) {
+      // pixels of the cell in raster order; weight alpha for o_a == o,
+      // 1 - alpha for o_b == o (both when o_a == o_b == o)
+      for (int ry = 0; ry < nrow; ++ry) {
+        const int base = ry * pitch;
+#pragma unroll 4
+        for (int rx = cx0; rx < cx1; ++rx) {
+          const int i = base + rx;
+          const int pk = sC[i];
+          const float al = sA[i];
+          const float4 g = sG[i];
+          const float wa = ((pk & 0xff) == lane_o) ? al : 0.0f;
+          const float wb = ((pk >> 8) == lane_o) ? 1.0f - al : 0.0f;
+          const float wt = wa + wb;
+          acc[0] = fmaf(wt, g.x, acc[0]);
+          acc[1] = fmaf(wt, g.y, acc[1]);
+          acc[2] = fmaf(wt, g.z, acc[2]);
+          acc[3] = fmaf(wt, g.w, acc[3]);
         }
       }
     }
     __syncthreads();
   }
-  if (a.S) {
+  if (scanner) {
+    const int64_t hw = (int64_t)a.h * a.w;
+    float* out = a.S + ((int64_t)lane_o * hw + (int64_t)qy * a.w + qx0 + lane_cell) * C;
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const int pr = threadIdx.x + u * kThreads;
-      if (pr >= n_pairs_grp) continue;
-      const int cell = pr / K2, o = pr - cell * K2;
-      float* out = a.S + (((int64_t)qy * a.w + qx0 + cell) * K2 + o) * C;
-#pragma unroll
-      for (int ch = 0; ch < 4; ++ch)
-        if (ch < C) out[ch] = acc[u][ch];
-    }
+    for (int ch = 0; ch < 4; ++ch)
+      if (ch < C) out[ch] = acc[ch];
   }
 }
 
 __global__ __launch_bounds__(256) void k_bwd_lr(const BwdArgs a) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= (int64_t)a.h * a.w) return;
+  const int64_t hw = (int64_t)a.h * a.w;
+  if (q >= hw) return;
   const int qy = (int)(q / a.w), qx = (int)(q - (int64_t)qy * a.w);
   const int k = a.k, r = k / 2, K2 = k * k, C = a.C;
   float acc[4] = {0.f, 0.f, 0.f, 0.f};
@@ -238,7 +263,7 @@ __global__ __launch_bounds__(256) void k_bwd_lr(const BwdArgs a) {
     // the cell c whose window offset o points at q: c = q - (o / k - r, o % k - r)
     const int cy = qy - (o / k - r), cx = qx - (o % k - r);
     if (cy < 0 || cy >= a.h || cx < 0 || cx >= a.w) continue;
-    const float* src = a.S + (((int64_t)cy * a.w + cx) * K2 + o) * C;
+    const float* src = a.S + ((int64_t)o * hw + (int64_t)cy * a.w + cx) * C;
 #pragma unroll
     for (int ch = 0; ch < 4; ++ch)
       if (ch < C) acc[ch] += src[ch];
@@ -249,16 +274,14 @@ __global__ __launch_bounds__(256) void k_bwd_lr(const BwdArgs a) {
     if (ch < C) out[ch] = acc[ch];
 }
 
-static void bwd_geometry(int s, int k, int C, int w, int& nb, int& rows_chunk) {
+// Cells per workgroup (one scan lane per (cell, offset)) and HR rows per
+// chunk, chunks shrunk until the LDS of a workgroup is at most 32 KiB.
+static void bwd_geometry(int s, int k, int w, int& nb, int& rows_chunk) {
   const int K2 = k * k;
-  nb = std::max(1, std::min(2 * kThreads / K2, w));
-  // limit the cells of a group so one HR row of it stays within a few strips
-  nb = std::min(nb, std::max(1, 512 / s));
-  const int bytes_per_px = 4 * (2 + C);
-  auto lds = [&](int n, int rc) { return bytes_per_px * rc * n * s; };
+  nb = std::max(1, std::min(kThreads / K2, w));
   rows_chunk = s;
-  while (rows_chunk > 1 && lds(nb, rows_chunk) > kLdsBudget) rows_chunk = (rows_chunk + 1) / 2;
-  while (nb > 1 && lds(nb, rows_chunk) > kLdsBudget) nb = (nb + 1) / 2;
+  while (rows_chunk > 1 && 16 * bwd_lds_words(k, nb, s, rows_chunk) > 32 * 1024) rows_chunk = (rows_chunk + 1) / 2;
+  while (nb > 1 && 16 * bwd_lds_words(k, nb, s, rows_chunk) > 32 * 1024) nb = (nb + 1) / 2;
 }
 
 }  // namespace glu
@@ -319,7 +342,7 @@ glu_status glu_apply_backward(const glu_theta* theta, const glu_image* T_low, co
   a.s = p->s;
   a.k = p->k;
   a.C = C;
-  bwd_geometry(p->s, p->k, C, w, a.nb, a.rows_chunk);
+  bwd_geometry(p->s, p->k, w, a.nb, a.rows_chunk);
   a.groups_x = ceil_div(w, a.nb);
   a.s_magic = (uint32_t)std::min<uint64_t>(0xffffffffull, (1ull << 32) / (uint64_t)p->s);
   const int P = (p->s % 4 == 0) ? 4 : 1;
@@ -333,21 +356,25 @@ glu_status glu_apply_backward(const glu_theta* theta, const glu_image* T_low, co
     if (P == 4 && (C == 3 || C == 1) && grad_T_hat->row_stride % 4 == 0 && al(grad_T_hat->data, 16)) v |= VEC_G;
     a.vec = v;
   }
-  const size_t lds = (size_t)4 * (2 + C) * a.rows_chunk * a.nb * p->s;
+  const size_t lds = (size_t)16 * bwd_lds_words(p->k, a.nb, p->s, a.rows_chunk);
   const int64_t groups = (int64_t)h * a.groups_x;
   if (groups > 0x7fffffff) return fail(GLU_ERR_UNSUPPORTED, "image too large");
   hipStream_t sm = (hipStream_t)stream;
-  if (T_low->dtype == GLU_F16) {
-    if (P == 4)
-      hipLaunchKernelGGL((k_bwd_block<__half, 4>), dim3((unsigned)groups), dim3(kThreads), lds, sm, a);
+  typedef void (*BwdKernel)(const BwdArgs);
+  const bool f16 = T_low->dtype == GLU_F16, k3 = p->k == 3;
+  BwdKernel kern;
+  if (P == 4) {
+    if (f16)
+      kern = k3 ? k_bwd_block<__half, 4, 3> : k_bwd_block<__half, 4, 0>;
     else
-      hipLaunchKernelGGL((k_bwd_block<__half, 1>), dim3((unsigned)groups), dim3(kThreads), lds, sm, a);
+      kern = k3 ? k_bwd_block<float, 4, 3> : k_bwd_block<float, 4, 0>;
   } else {
-    if (P == 4)
-      hipLaunchKernelGGL((k_bwd_block<float, 4>), dim3((unsigned)groups), dim3(kThreads), lds, sm, a);
+    if (f16)
+      kern = k3 ? k_bwd_block<__half, 1, 3> : k_bwd_block<__half, 1, 0>;
     else
-      hipLaunchKernelGGL((k_bwd_block<float, 1>), dim3((unsigned)groups), dim3(kThreads), lds, sm, a);
+      kern = k3 ? k_bwd_block<float, 1, 3> : k_bwd_block<float, 1, 0>;
   }
+  hipLaunchKernelGGL(kern, dim3((unsigned)groups), dim3(kThreads), lds, sm, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "backward pass 1 launch");
   if (grad_T_low) {
