@@ -1,18 +1,22 @@
 #!/usr/bin/env python3
 """Throughput of the guided linear upsampling hot path on one MI355X.
 
-One step = the pair search (Eq. 3-4, every pair of the 3 x 3 window) plus the
+One step = the pair search (Eq. 3-4, every pair of the 3 x 3 window) and the
 apply step (Eq. 1) over one 3840 x 2160 RGB float32 frame downsampled x8
-(480 x 270), eps = 1e-3, launched as the two kernels glu_search and
-glu_apply.  Inputs are seeded synthetic Voronoi frames (the 4K x8 workload:
-1000 cells, 400 dots of 1-3 px, sigma 0.01, regular-grid downsampling, LR
-operator f1) already resident in HBM; five buffer sets (about 1.2 GB) are
-rotated so the 256 MB last-level cache cannot serve repeats.
+(480 x 270), eps = 1e-3, as one fused glu_search_apply launch that writes
+both Theta and T_hat.  Inputs are seeded synthetic Voronoi frames (the 4K x8
+workload: 1000 cells, 400 dots of 1-3 px, sigma 0.01, regular-grid
+downsampling, LR operator f1) already resident in HBM; five buffer sets
+(about 1.2 GB) are rotated so the 256 MB last-level cache cannot serve
+repeats.
 
-Prints ONE JSON line (see the keys below).  Extra per-kernel timings (search,
-apply, fused search+apply, the fast search of Algorithm 1) and the roofline
-of the dominant kernel are measured live with HIP events on the stream the
-kernels run on.
+Prints ONE JSON line.  Beside the headline it carries, measured live with
+HIP events on the stream the kernels run on: per-kernel times of both search
+modes (search, apply, fused, and the two-kernel step), the roofline of the
+dominant kernel, the backward pass, and one entry per further workload:
+plain 512 x 512 x4, joint downsampling 2048 x 2048 x8 (5 rounds), 60 x 4K
+float16 video frames in one graph-captured persistent launch, an uneven
+batch of 64 images with autotuned tiles, and the backward over 16 x 1024^2.
 """
 from __future__ import annotations
 
@@ -39,25 +43,28 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3
 # 36 pairs).  Exhaustive: 27 (I - L_j for 9 cells) + 5 (|d_0|^2) + 36 x 17
 # (dot 5, weight 1, residual 6, squared norm 5).  Fast (Algorithm 1):
 # 9 x (3 + 5 + 1 sqrt) for the distances, then 9 x (1 + 1 + 1 division
-# + 1 + 6 + 6 + 5) for the partners.
+# + 1 + 6 + 6 + 5) for the partners.  The fused kernel adds Eq. 1 (3 x 2).
 FLOPS_PER_PX = {"exhaustive": 27 + 5 + 36 * 17, "fast": 9 * 9 + 9 * 21}
+APPLY_FLOPS_PER_PX = 6
 # Algorithmic HBM bytes per HR pixel (C = 3, float32): search reads I (12)
 # and writes Theta (6); apply reads Theta (6) and writes T_hat (12); fused
-# reads I and writes Theta and T_hat.
-BYTES_PER_PX = {"search": 18, "apply": 18, "step": 36, "fused": 30, "bwd": 22}
+# reads I and writes Theta and T_hat; backward reads G (12) and Theta (6)
+# and writes dalpha (4).
+BYTES_PER_PX = {"search": 18, "apply": 18, "two_kernel": 36, "fused": 30, "bwd": 22}
 
 
 def _parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=300)
+    ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--mode", choices=["exhaustive", "fast"], default="exhaustive")
     ap.add_argument("--sets", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--only", choices=["all", "step"], default="all",
                     help="'step' times only the headline step (for profiling)")
+    ap.add_argument("--no-configs", action="store_true", help="skip the further workloads")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (a known-size reference for HBM counters)")
     return ap.parse_args()
@@ -72,7 +79,7 @@ def _kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def _traffic(kernel_key: str, n_px: int):
+def _traffic(kernel_key: str):
     """HBM bytes per launch from the committed counter summary, or None when
     the kernel sources changed since the counters were taken."""
     p = os.path.join(ROOT, "profiles", "traffic_4k_x8.json")
@@ -88,6 +95,39 @@ def _traffic(kernel_key: str, n_px: int):
     if not ent:
         return None
     return ent.get("hbm_bytes_per_launch")
+
+
+def _events_ms(torch, stream, fn, steps, warmup):
+    """Average ms per call of fn() over `steps` calls, HIP events on `stream`."""
+    for i in range(warmup):
+        fn(i)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for i in range(steps):
+        fn(i)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def _lr_f1_torch(torch, c):
+    """LR operator f1 (colour matrix, then gamma 0.8) on the GPU in float32."""
+    import synth
+
+    M = torch.tensor(synth.COLOR_MATRIX, dtype=torch.float32, device=c.device)
+    return torch.clamp(c.float() @ M.T, min=0.0) ** 0.8
+
+
+def _noisy_crop(torch, canvas_dev, y0, x0, h, w, seed, dtype):
+    """A crop of a noise-free Voronoi canvas plus seeded N(0, 0.01) noise
+    drawn on the GPU, clipped to [0, 1]."""
+    g = torch.Generator(device=canvas_dev.device)
+    g.manual_seed(seed)
+    img = canvas_dev[y0:y0 + h, x0:x0 + w]
+    noise = torch.randn(img.shape, generator=g, device=img.device, dtype=torch.float32)
+    return torch.clamp(img + 0.01 * noise, 0.0, 1.0).to(dtype).contiguous()
 
 
 def main():
@@ -118,70 +158,66 @@ def main():
         out = torch.empty((H, W, 3), dtype=torch.float32, device=dev)
         sets.append(dict(I=I, Il=Il, T=T, th=th, out=out))
     torch.cuda.synchronize()
-    gen_s = time.time() - t0
-    print("inputs ready in %.1f s" % gen_s, file=sys.stderr, flush=True)
+    print("inputs ready in %.1f s" % (time.time() - t0), file=sys.stderr, flush=True)
 
     stream = torch.cuda.current_stream()
     n_px = H * W
 
-    def step(i, mode):
-        st = sets[i % len(sets)]
-        glu.search(st["I"], st["Il"], S, K, EPS, mode, theta=st["th"])
-        glu.apply(st["th"], st["T"], S, K, out=st["out"])
+    def fused(mode):
+        def f(i):
+            st = sets[i % len(sets)]
+            glu.search_apply(st["I"], st["Il"], st["T"], S, K, EPS, mode, theta=st["th"], out=st["out"])
+        return f
 
-    def search_only(i, mode):
-        st = sets[i % len(sets)]
-        glu.search(st["I"], st["Il"], S, K, EPS, mode, theta=st["th"])
+    def two_kernel(mode):
+        def f(i):
+            st = sets[i % len(sets)]
+            glu.search(st["I"], st["Il"], S, K, EPS, mode, theta=st["th"])
+            glu.apply(st["th"], st["T"], S, K, out=st["out"])
+        return f
 
-    def apply_only(i, mode):
-        st = sets[i % len(sets)]
-        glu.apply(st["th"], st["T"], S, K, out=st["out"])
+    def search_only(mode):
+        def f(i):
+            st = sets[i % len(sets)]
+            glu.search(st["I"], st["Il"], S, K, EPS, mode, theta=st["th"])
+        return f
 
-    def fused(i, mode):
-        st = sets[i % len(sets)]
-        glu.search_apply(st["I"], st["Il"], st["T"], S, K, EPS, mode, theta=st["th"], out=st["out"])
+    def apply_only(mode):
+        def f(i):
+            st = sets[i % len(sets)]
+            glu.apply(st["th"], st["T"], S, K, out=st["out"])
+        return f
 
-    def timed(fn, mode, steps, warmup):
-        for i in range(warmup):
-            fn(i, mode)
-        torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for i in range(steps):
-            fn(i, mode)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        return e0.elapsed_time(e1) / steps  # ms
-
-    # headline: timed region bracketed by synchronisation on both sides
+    # headline: W warmup steps, then exactly K timed steps bracketed by
+    # synchronisation on both sides
+    step = fused(args.mode)
     for i in range(args.warmup):
-        step(i, args.mode)
+        step(i)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     wall0 = time.perf_counter()
     e0.record(stream)
     for i in range(args.steps):
-        step(i, args.mode)
+        step(i)
     e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
     ms_step = e0.elapsed_time(e1) / args.steps
     value = n_px / (ms_step * 1e-3) / 1e6
+    print("headline done: %.2f us/step" % (1e3 * ms_step), file=sys.stderr, flush=True)
 
     kern = {}
     other = "fast" if args.mode == "exhaustive" else "exhaustive"
     if args.only == "all":
         for mode in (args.mode, other):
             kern[mode] = dict(
-                search_us=1e3 * timed(search_only, mode, args.steps, 3),
-                apply_us=1e3 * timed(apply_only, mode, args.steps, 3),
-                fused_us=1e3 * timed(fused, mode, args.steps, 3),
-                step_us=1e3 * timed(step, mode, args.steps, 3),
+                search_us=1e3 * _events_ms(torch, stream, search_only(mode), args.steps, 20),
+                apply_us=1e3 * _events_ms(torch, stream, apply_only(mode), args.steps, 20),
+                fused_us=1e3 * _events_ms(torch, stream, fused(mode), args.steps, 20),
+                two_kernel_us=1e3 * _events_ms(torch, stream, two_kernel(mode), args.steps, 20),
             )
-    else:
-        kern[args.mode] = dict(search_us=float("nan"))
+        print("kernel timings done", file=sys.stderr, flush=True)
 
     bwd = None
     if args.only == "all":
@@ -191,11 +227,11 @@ def main():
         gT = torch.empty((H // S, W // S, 3), dtype=torch.float32, device=dev)
         ga = torch.empty((H, W), dtype=torch.float32, device=dev)
 
-        def backward(i, mode):
+        def backward(i):
             st = sets[i % len(sets)]
             glu.apply_backward(st["th"], st["T"], G, S, K, workspace=ws, out_T_low=gT, out_alpha=ga)
 
-        bwd_ms = timed(backward, args.mode, args.steps, 3)
+        bwd_ms = _events_ms(torch, stream, backward, args.steps, 20)
         bwd = {
             "us": round(1e3 * bwd_ms, 2),
             "Mpx_s": round(n_px / (bwd_ms * 1e-3) / 1e6, 1),
@@ -203,27 +239,30 @@ def main():
             "hbm_frac": round(BYTES_PER_PX["bwd"] * n_px / (bwd_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         }
 
-    ks = kern[args.mode]
     roof = None
     if args.only == "all":
-        flops = FLOPS_PER_PX[args.mode] * n_px
-        achieved = flops / (ks["search_us"] * 1e-6) / 1e12
-        traffic = _traffic("search_" + args.mode, n_px)
+        ks = kern[args.mode]
+        flops = (FLOPS_PER_PX[args.mode] + APPLY_FLOPS_PER_PX) * n_px
+        achieved = flops / (ks["fused_us"] * 1e-6) / 1e12
         roof = {
-            "kernel": "search_" + args.mode,
+            "kernel": "search_%s_fused" % args.mode,
             "bound": "alu",
             "achieved": round(achieved, 3),
             "peak": FP32_VECTOR_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
-            "traffic": traffic,
+            "traffic": _traffic("search_%s_fused" % args.mode),
         }
+
+    configs = None
+    if args.only == "all" and not args.no_configs:
+        configs = _configs(np, torch, synth, glu, dev, stream, scene)
 
     cpu = None
     if not args.no_cpu_baseline:
         cpu = _cpu_baseline(scene, args.mode, args.cpu_seconds)
 
-    step_gbs = BYTES_PER_PX["step"] * n_px / (ms_step * 1e-3) / 1e9
+    step_gbs = BYTES_PER_PX["fused"] * n_px / (ms_step * 1e-3) / 1e9
     res = {
         "metric": "HR Mpixel/s, GLU search+apply, 4K x8 fp32",
         "value": round(value, 1),
@@ -239,30 +278,32 @@ def main():
         "data": "synthetic (seeded Voronoi frames, inputs resident in HBM)",
         "config": {
             "workload": "3840x2160 RGB fp32, x8 point downsample to 480x270, 3x3 window, eps 1e-3, "
-                        "%s pair search + apply (two kernels)" % args.mode,
+                        "%s pair search + apply, one fused launch writing Theta and T_hat" % args.mode,
             "mode": args.mode,
             "H": H, "W": W, "s": S, "k": K,
             "buffer_sets": len(sets),
         },
         "hbm": {
-            "bytes_per_px": BYTES_PER_PX["step"],
+            "bytes_per_px": BYTES_PER_PX["fused"],
             "achieved_GBps": round(step_gbs, 1),
             "peak_GBps": HBM_PEAK_GBS,
             "frac": round(step_gbs / HBM_PEAK_GBS, 4),
         },
         "roofline": roof,
+        "cpu_baseline": cpu,
         "kernels_us": {m: {k2: round(v, 2) for k2, v in d.items()} for m, d in kern.items()},
         "bwd": bwd,
-        "cpu_baseline": cpu,
+        "configs": configs,
         "wall_s_timed_region": round(wall, 4),
     }
     if args.only == "all":
         for m, d in kern.items():
             res.setdefault("modes", {})[m] = {
-                "step_Mpx_s": round(n_px / d["step_us"], 1),
                 "fused_Mpx_s": round(n_px / d["fused_us"], 1),
-                "step_hbm_frac": round(BYTES_PER_PX["step"] * n_px / (d["step_us"] * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
+                "two_kernel_Mpx_s": round(n_px / d["two_kernel_us"], 1),
                 "fused_hbm_frac": round(BYTES_PER_PX["fused"] * n_px / (d["fused_us"] * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
+                "two_kernel_hbm_frac": round(
+                    BYTES_PER_PX["two_kernel"] * n_px / (d["two_kernel_us"] * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
                 "apply_hbm_frac": round(BYTES_PER_PX["apply"] * n_px / (d["apply_us"] * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
             }
     if args.calib_copy:
@@ -273,6 +314,141 @@ def main():
         torch.cuda.synchronize()
         res["calib_copy_bytes"] = 4 * src.numel()
     print(json.dumps(res), flush=True)
+
+
+def _configs(np, torch, synth, glu, dev, stream, scene):
+    """The further workloads, each timed with HIP events on `stream`."""
+    out = {}
+
+    # plain GLU, 512 x 512, box x4 to 128 x 128 (cache-resident)
+    I = torch.from_numpy(synth.voronoi(512, 512, n_cells=64, n_dots=20, dot_px=(2, 4), seed=1)).to(dev)
+    Il = glu.downsample(I, 4, "box")
+    T = _lr_f1_torch(torch, Il).contiguous()
+    th = glu.empty_theta(512, 512, dev)
+    o = torch.empty_like(I)
+    r = {}
+    for mode in ("exhaustive", "fast"):
+        ms = _events_ms(torch, stream, lambda i: glu.search_apply(I, Il, T, 4, 3, EPS, mode, theta=th, out=o), 200, 20)
+        r[mode] = {"us": round(1e3 * ms, 2), "Mpx_s": round(512 * 512 / (ms * 1e-3) / 1e6, 1)}
+    out["plain_512_box4"] = r
+    print("plain 512 done", file=sys.stderr, flush=True)
+
+    # joint downsampling, 2048 x 2048 x8, 5 rounds (Algorithm 2)
+    I = torch.from_numpy(synth.voronoi(2048, 2048, n_cells=512, n_dots=200, dot_px=(1, 3), seed=2)).to(dev)
+    L0 = glu.downsample(I, 8, "point")
+    jws = None
+    r = {}
+    for mode in ("exhaustive", "fast"):
+        walls = []
+        stats = None
+        for rep in range(3):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            Lj, thj, ej, stats, _ = glu.joint_downsample(I, L0, 8, 3, EPS, mode, max_iter=5, log_capacity=0,
+                                                         workspace=jws)
+            torch.cuda.synchronize()
+            walls.append(time.perf_counter() - t)
+        r[mode] = {
+            "wall_ms": round(1e3 * sorted(walls)[1], 3),
+            "Mpx_s": round(2048 * 2048 / sorted(walls)[1] / 1e6, 1),
+            "rounds_run": stats["rounds_run"],
+            "n_large": stats["n_large"][: stats["rounds_run"]],
+            "n_components": stats["n_components"][: stats["rounds_run"]],
+            "n_accepted": stats["n_accepted"][: stats["rounds_run"]],
+            "err_sum_initial": round(stats["err_sum_initial"], 3),
+            "err_sum_final": round(stats["err_sum_final"], 3),
+        }
+    out["joint_2048_x8_5rounds"] = r
+    print("joint done", file=sys.stderr, flush=True)
+    del I, L0
+
+    # 60 frames of 3840 x 2160, float16 storage, one persistent launch under
+    # a captured graph; frame t is the scene crop at column 3 t
+    canvas = torch.from_numpy(scene.canvas.astype(np.float32)).to(dev)
+    items = []
+    for t in range(60):
+        If = _noisy_crop(torch, canvas, 0, 3 * t, H, W, 7000 + t, torch.float16)
+        Ilf = glu.downsample(If, S, "point")
+        items.append(dict(I=If, I_low=Ilf, T_low=_lr_f1_torch(torch, Ilf).half().contiguous(),
+                          T_hat=torch.empty((H, W, 3), dtype=torch.float16, device=dev), s=S, k=K))
+    del canvas
+    r = {}
+    for mode in ("exhaustive", "fast"):
+        plan = glu.BatchPlan(items, mode=mode)
+        g = plan.capture_graph()
+        ms = _events_ms(torch, stream, lambda i: g.replay(), 10, 2)
+        ms_launch = _events_ms(torch, stream, lambda i: plan.launch(), 10, 2)
+        npx = 60 * H * W
+        r[mode] = {"graph_ms": round(ms, 3), "Mpx_s": round(npx / (ms * 1e-3) / 1e6, 1),
+                   "frames_per_s": round(60 / (ms * 1e-3), 1), "launch_ms": round(ms_launch, 3),
+                   "hbm_frac": round(12 * npx / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        del g
+        plan.close()
+    out["video_60x4k_f16_graph"] = r
+    del items
+    torch.cuda.synchronize()
+    print("video done", file=sys.stderr, flush=True)
+
+    # uneven batch: 64 images, sizes 720x480 .. 6000x4000, s in {4, 8, 16},
+    # k in {3, 5}; crops of one seeded canvas with the same cell density
+    specs = synth.uneven_batch_specs(64, seed=4)
+    big = synth.make_scene(4000, 6000, 2894, 1157, (1, 3), seed=4)
+    canvas = torch.from_numpy(big.canvas.astype(np.float32)).to(dev)
+    rng = np.random.default_rng(44)
+    items = []
+    for i, sp in enumerate(specs):
+        y0 = int(rng.integers(0, 4000 - sp["H"] + 1))
+        x0 = int(rng.integers(0, 6000 - sp["W"] + 1))
+        Iu = _noisy_crop(torch, canvas, y0, x0, sp["H"], sp["W"], sp["seed"], torch.float32)
+        Ilu = glu.downsample(Iu, sp["s"], "point")
+        items.append(dict(I=Iu, I_low=Ilu, T_low=_lr_f1_torch(torch, Ilu).contiguous(),
+                          T_hat=torch.empty_like(Iu), s=sp["s"], k=sp["k"]))
+    del canvas
+    r = {}
+    npx = sum(sp["H"] * sp["W"] for sp in specs)
+    for mode in ("exhaustive", "fast"):
+        seen = set()
+        tuned = {}
+        for it in items:
+            key = (it["s"], it["k"])
+            if key not in seen:
+                seen.add(key)
+                tuned["s%d_k%d" % key] = glu.autotune(it, mode=mode)
+        plan = glu.BatchPlan(items, mode=mode)
+        ms = _events_ms(torch, stream, lambda i: plan.launch(), 5, 1)
+        r[mode] = {"ms": round(ms, 3), "Mpx_s": round(npx / (ms * 1e-3) / 1e6, 1), "tile_variants": tuned,
+                   "hbm_frac": round(24 * npx / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        plan.close()
+    out["uneven_64"] = dict(r, n_images=len(specs), Mpx=round(npx / 1e6, 1))
+    del items
+    torch.cuda.synchronize()
+    print("uneven done", file=sys.stderr, flush=True)
+
+    # backward over a batch of 16 x 1024 x 1024, x8, Theta from the search
+    canvas = torch.from_numpy(scene.canvas.astype(np.float32)).to(dev)
+    bat = []
+    gen = torch.Generator(dev)
+    gen.manual_seed(16)
+    for b in range(16):
+        Ib = _noisy_crop(torch, canvas, (b % 2) * 1000, (b // 2) * 370, 1024, 1024, 8000 + b, torch.float32)
+        Ilb = glu.downsample(Ib, 8, "point")
+        Tb = _lr_f1_torch(torch, Ilb).contiguous()
+        thb = glu.search(Ib, Ilb, 8, 3, EPS)
+        G = torch.randn((1024, 1024, 3), generator=gen, device=dev)
+        bat.append((thb, Tb, G, torch.empty_like(Tb), torch.empty((1024, 1024), device=dev)))
+    del canvas
+    ws = torch.empty(glu.apply_backward_workspace(1024, 1024, 3, 8, 3) // 4 + 1, device=dev)
+
+    def bwd_batch(i):
+        for thb, Tb, G, gT, ga in bat:
+            glu.apply_backward(thb, Tb, G, 8, 3, workspace=ws, out_T_low=gT, out_alpha=ga)
+
+    ms = _events_ms(torch, stream, bwd_batch, 20, 3)
+    npx = 16 * 1024 * 1024
+    out["bwd_16x1024"] = {"ms": round(ms, 4), "Mpx_s": round(npx / (ms * 1e-3) / 1e6, 1),
+                          "hbm_frac": round(BYTES_PER_PX["bwd"] * npx / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    print("bwd batch done", file=sys.stderr, flush=True)
+    return out
 
 
 def _cpu_baseline(scene, mode, seconds):

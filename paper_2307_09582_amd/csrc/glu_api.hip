@@ -130,7 +130,7 @@ __global__ __launch_bounds__(kThreads) void k_search(const ImgDesc d, float eps)
   extern __shared__ float4 smem[];
   const int tile = blockIdx.x;
   const int ty = tile / d.tiles_x, tx = tile - ty * d.tiles_x;
-  search_tile<KW, P, MODE, T, FUSED, (MODE == MODE_EXH && KW > 0)>(d, ty, tx, eps, smem);
+  search_tile<KW, P, MODE, T, FUSED, uses_pair_table(MODE, KW)>(d, ty, tx, eps, smem);
 }
 
 // One workgroup per tile of one LR row by d.tqx LR columns.
@@ -265,7 +265,7 @@ static glu_status run_search(const glu_image* I, const glu_image* I_low, const g
   d.C = C;
   d.dtype = I->dtype;
   const int mode = p->mode == GLU_SEARCH_FAST ? MODE_FAST : MODE_EXH;
-  const bool table = mode == MODE_EXH && (p->k == 3 || p->k == 5);
+  const bool table = uses_pair_table(mode, p->k);
   const TileChoice tc = choose_tile(p->s, p->k, mode, fused, table, tuned_variant(mode, p->k, p->s, I->dtype));
   fill_tiles(d, tc);
   d.vec = launch_vec_flags(d, tc.P, dtype_size(I->dtype));

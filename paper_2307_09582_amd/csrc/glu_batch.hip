@@ -71,11 +71,11 @@ __device__ __forceinline__ void run_tile(const ImgDesc& d, int ty, int tx, float
     }
   } else if (kc == 1) {
     if (pc == 0) {
-      if (dt == 0) search_tile<5, 4, MODE, float, true, MODE == MODE_EXH>(d, ty, tx, eps, smem);
-      else search_tile<5, 4, MODE, __half, true, MODE == MODE_EXH>(d, ty, tx, eps, smem);
+      if (dt == 0) search_tile<5, 4, MODE, float, true, false>(d, ty, tx, eps, smem);
+      else search_tile<5, 4, MODE, __half, true, false>(d, ty, tx, eps, smem);
     } else {
-      if (dt == 0) search_tile<5, 1, MODE, float, true, MODE == MODE_EXH>(d, ty, tx, eps, smem);
-      else search_tile<5, 1, MODE, __half, true, MODE == MODE_EXH>(d, ty, tx, eps, smem);
+      if (dt == 0) search_tile<5, 1, MODE, float, true, false>(d, ty, tx, eps, smem);
+      else search_tile<5, 1, MODE, __half, true, false>(d, ty, tx, eps, smem);
     }
   } else {
     if (pc == 0) {
@@ -166,7 +166,7 @@ static glu_status make_item(const glu_batch_item& it, const glu_params& p, int m
   d.k = it.k;
   d.C = it.T_low.channels;
   d.dtype = it.I.dtype;
-  const bool table = mode == MODE_EXH && (it.k == 3 || it.k == 5);
+  const bool table = uses_pair_table(mode, it.k);
   const int var = variant_override >= 0 ? variant_override : tuned_variant(mode, it.k, it.s, it.I.dtype);
   const TileChoice tc = choose_tile(it.s, it.k, mode, true, table, var);
   fill_tiles(d, tc);

@@ -496,9 +496,82 @@ __device__ __forceinline__ void fast_strip(const float (&ip)[P][3], const Win& w
 }
 
 // ---------------------------------------------------------------------------
+// Staged output stores of the fused search
+// ---------------------------------------------------------------------------
+// A strip of 4 pixels of C = 3 (or 1) channels is 3 (or 1) words of 4
+// elements (16 bytes in float32, 8 in float16).  Lane l writes the words
+// of its strip to slots 3l .. 3l+2 (or l) of its wave's LDS buffer.
+template <typename T, int P>
+__device__ __forceinline__ void stage_strip(float4* buf, int lane, int C, const float (&o)[P][4]) {
+  if constexpr (P == 4) {
+    if constexpr (sizeof(T) == 4) {
+      if (C == 3) {
+        buf[3 * lane + 0] = make_float4(o[0][0], o[0][1], o[0][2], o[1][0]);
+        buf[3 * lane + 1] = make_float4(o[1][1], o[1][2], o[2][0], o[2][1]);
+        buf[3 * lane + 2] = make_float4(o[2][2], o[3][0], o[3][1], o[3][2]);
+      } else {
+        buf[lane] = make_float4(o[0][0], o[1][0], o[2][0], o[3][0]);
+      }
+    } else {
+      uint2* b2 = reinterpret_cast<uint2*>(buf);
+      auto pk = [](float a, float b) {
+        return (uint32_t)__half_as_ushort(__float2half_rn(a)) | ((uint32_t)__half_as_ushort(__float2half_rn(b)) << 16);
+      };
+      if (C == 3) {
+        b2[3 * lane + 0] = make_uint2(pk(o[0][0], o[0][1]), pk(o[0][2], o[1][0]));
+        b2[3 * lane + 1] = make_uint2(pk(o[1][1], o[1][2]), pk(o[2][0], o[2][1]));
+        b2[3 * lane + 2] = make_uint2(pk(o[2][2], o[3][0]), pk(o[3][1], o[3][2]));
+      } else {
+        b2[lane] = make_uint2(pk(o[0][0], o[1][0]), pk(o[2][0], o[3][0]));
+      }
+    }
+  }
+}
+
+// Stores the staged strips of the calling wave.  off = element offset of
+// the lane's own strip in `out`, or -1 when the lane staged nothing; every
+// lane of the wave must call this together.
+template <typename T>
+__device__ __forceinline__ void store_staged(float4* buf, int lane, int C, int64_t off, T* __restrict__ out) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  const int lo = (int)(uint32_t)off, hi = (int)(off >> 32);
+  const int nw = C == 3 ? 3 : 1;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    if (k >= nw) break;
+    const int idx = lane + 64 * k;
+    const int st = nw == 3 ? idx / 3 : idx;  // strip (owner lane) of the word
+    const int part = idx - st * nw;
+    const int64_t o = ((int64_t)__shfl(hi, st, 64) << 32) | (uint32_t)__shfl(lo, st, 64);
+    if (o >= 0) {
+      T* dst = out + o + 4 * part;
+      if constexpr (sizeof(T) == 4)
+        __builtin_nontemporal_store(reinterpret_cast<const f32x4*>(buf)[idx], reinterpret_cast<f32x4*>(dst));
+      else
+        __builtin_nontemporal_store(reinterpret_cast<const u32x2*>(buf)[idx], reinterpret_cast<u32x2*>(dst));
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// ---------------------------------------------------------------------------
 // One tile of search (+ apply when FUSED)
 // ---------------------------------------------------------------------------
 enum { MODE_EXH = 0, MODE_FAST = 1 };
+
+// The exhaustive search reads per-cell pair constants from an LDS table for
+// 3 x 3 windows (36 pairs, 1152 bytes per LR cell).  Larger windows (300
+// pairs for 5 x 5) would shrink the tiles below one strip per thread, so
+// they build the constants of each pair once per strip instead.
+__host__ __device__ constexpr bool uses_pair_table(int mode, int k) { return mode == MODE_EXH && k == 3; }
+
+// Output staging of the fused search: per wave, 64 strips of 4 pixels of 3
+// float channels (48 bytes each).
+constexpr int kStageWords = (kThreads / 64) * 64 * 3;
 
 // LDS float4 words one search tile needs.
 __host__ __device__ inline int search_tile_words(int tqy, int tqx, int k, int mode, bool fused, bool table) {
@@ -506,6 +579,7 @@ __host__ __device__ inline int search_tile_words(int tqy, int tqx, int k, int mo
   const int ncell = (tqy + 2 * r) * (tqx + 2 * r);
   int words = ncell * (fused ? 2 : 1);
   if (mode == MODE_EXH && table) words += 2 * tqy * tqx * (n_pairs(k * k) + 1);
+  if (fused) words += kStageWords;
   return words;
 }
 
@@ -550,6 +624,10 @@ __device__ __forceinline__ void search_tile(const ImgDesc& d, int ty, int tx, fl
   float4* sT = FUSED ? smem + ncell : nullptr;
   PairK* sTab = reinterpret_cast<PairK*>(smem + (FUSED ? 2 : 1) * ncell);
   const int tstride = n_pairs(K2) + 1;
+  const int lane = (int)threadIdx.x & 63;
+  // per-wave output staging (fused): after the pair table
+  float4* sStage = smem + (FUSED ? 2 : 1) * ncell +
+                   ((MODE == MODE_EXH && TABLE) ? 2 * tqy * tqx * tstride : 0) + ((int)threadIdx.x >> 6) * 64 * 3;
 
   const int rows = tqy * s, cols = tqx * s;
   const int spr = cols / P;
@@ -590,7 +668,13 @@ __device__ __forceinline__ void search_tile(const ImgDesc& d, int ty, int tx, fl
     __syncthreads();
   }
 
-  for (int t = threadIdx.x; t < nstrips; t += kThreads) {
+  // Fused tiles whose T_hat rows allow vector stores hand the full strips of
+  // a wave to one staged store: the strips' values go to LDS and every lane
+  // then stores 4-element words of consecutive strips, so neighbouring
+  // lanes write neighbouring words of a row.  The loop is uniform over a
+  // wave for that; lanes past the tile or the image only take part in it.
+  const bool staged = FUSED && P == 4 && vecT && (d.C == 3 || d.C == 1);
+  for (int t = threadIdx.x; t - lane < nstrips; t += kThreads) {
     const int ry = t / spr;
     const int rx = (t - ry * spr) * P;
     const int y = qy0 * s + ry, x = qx0 * s + rx;
@@ -600,11 +684,13 @@ __device__ __forceinline__ void search_tile(const ImgDesc& d, int ty, int tx, fl
 #pragma unroll
       for (int c = 0; c < 3; ++c) ip[q][c] = ipn[q][c];
     prefetch(t + kThreads);
-    if (y >= d.H || x >= d.W) continue;
+    const bool live = t < nstrips && y < d.H && x < d.W;
+    const bool full = interior || (x + P <= d.W);
+    int64_t stage_off = -1;  // element offset of a staged strip in T_hat
+    if (live) {
     const int cy = ry / s, cx = rx / s;
     const LdsWin<KW> win{sL + cy * lx + cx, lx, kw};
     const PairK* tab = sTab + (cy * tqx + cx) * tstride;
-    const bool full = interior || (x + P <= d.W);
     float best[P], al[P];
     int code[P];
     if (MODE == MODE_EXH) {
@@ -644,8 +730,15 @@ __device__ __forceinline__ void search_tile(const ImgDesc& d, int ty, int tx, fl
         o[q][2] = fmaf(al[q], Ta.z - Tb.z, Tb.z);
         o[q][3] = fmaf(al[q], Ta.w - Tb.w, Tb.w);
       }
-      store_out<T, P>(static_cast<T*>(d.That) + (int64_t)y * d.That_stride, x, d.W, d.C, vecT, full, o);
+      if (staged && full) {
+        stage_strip<T, P>(sStage, lane, d.C, o);
+        stage_off = (int64_t)y * d.That_stride + (int64_t)x * d.C;
+      } else {
+        store_out<T, P>(static_cast<T*>(d.That) + (int64_t)y * d.That_stride, x, d.W, d.C, vecT, full, o);
+      }
     }
+    }  // live
+    if (staged) store_staged<T>(sStage, lane, d.C, stage_off, static_cast<T*>(d.That));
   }
 }
 

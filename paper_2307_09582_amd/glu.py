@@ -231,7 +231,8 @@ def joint_downsample(I, I_low0, s, k=3, eps=EPS, mode="exhaustive", tau=TAU, max
     """Algorithm 2 (joint down/upsampling).  Returns (I_low, Theta, E, stats, log).
 
     I_low0 is not modified (a copy is optimised).  stats is a dict of the
-    per-round counts; log a list of per-trial dicts in the sequential order.
+    per-round counts; log a list of per-trial dicts in the sequential order
+    (empty, and not recorded, when log_capacity is 0).
     """
     H, W = I.shape[:2]
     I_low = I_low0.clone()
@@ -245,6 +246,7 @@ def joint_downsample(I, I_low0, s, k=3, eps=EPS, mode="exhaustive", tau=TAU, max
     st = L.glu_jd_stats()
     cap = int(log_capacity if log_capacity is not None else max(1024, H * W // 16))
     qcap = int(q_capacity if q_capacity is not None else 4 * cap)
+    cap, qcap = max(cap, 0), max(qcap, 0)
     arrs = dict(
         round=(C.c_int32 * cap)(), first_pixel=(C.c_int32 * cap)(), accepted=(C.c_uint8 * cap)(),
         e0=(C.c_double * cap)(), e1=(C.c_double * cap)(), n_q=(C.c_int32 * cap)(),
@@ -264,7 +266,7 @@ def joint_downsample(I, I_low0, s, k=3, eps=EPS, mode="exhaustive", tau=TAU, max
             C.c_void_p(workspace.data_ptr()),
             ws_bytes,
             C.byref(st),
-            C.byref(lg),
+            C.byref(lg) if cap > 0 else None,
             _stream(),
         )
     )
