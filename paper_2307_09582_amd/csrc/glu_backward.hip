@@ -93,17 +93,17 @@ __device__ __forceinline__ void load_grad(const float* __restrict__ row, int x, 
 }
 
 // LDS float4 words of pass 1: staged LR target cells, then per pixel slot of
-// a chunk a float4 of gradients, a float alpha and a uint16 code pair.
+// a chunk a float4 (gradients, with alpha in .w when C <= 3), a float alpha
+// (C == 4) and a uint16 code pair, then (k = 3) the code decoding table.
 __host__ __device__ inline int bwd_lds_words(int k, int nb, int s, int rows_chunk) {
   const int n = rows_chunk * nb * s;
-  return k * (nb + k - 1) + n + (n + 3) / 4 + (n + 7) / 8;
+  return k * (nb + k - 1) + n + (n + 3) / 4 + (n + 7) / 8 + (k == 3 ? (81 + 3) / 4 : 0);
 }
 
-template <typename T, int P, int KW>
-__global__ __launch_bounds__(kThreads) void k_bwd_block(const BwdArgs a) {
-  extern __shared__ float4 smem[];
+template <typename T, int P, int KW, int C>
+__device__ __forceinline__ void bwd_block(const BwdArgs& a, float4* smem) {
   const int k = KW > 0 ? KW : a.k;
-  const int r = k / 2, K2 = k * k, s = a.s, C = a.C;
+  const int r = k / 2, K2 = k * k, s = a.s;
   const int qy = blockIdx.x / a.groups_x;
   const int qx0 = (blockIdx.x - qy * a.groups_x) * a.nb;
   const int nb = min(a.nb, a.w - qx0);
@@ -114,6 +114,9 @@ __global__ __launch_bounds__(kThreads) void k_bwd_block(const BwdArgs a) {
   float4* sG = smem + k * lx;
   float* sA = reinterpret_cast<float*>(sG + nslot);
   uint16_t* sC = reinterpret_cast<uint16_t*>(sA + ((nslot + 3) & ~3));
+  // k = 3: code -> LDS offset of cell a | of cell b << 8 | (o_a | o_b << 8) << 16
+  // (offsets (o / 3) * lx + o % 3 < 256 because nb <= 28)
+  uint32_t* sDec = reinterpret_cast<uint32_t*>(sC + ((nslot + 7) & ~7));
   const T* __restrict__ TL = static_cast<const T*>(a.T);
   const bool vecTh = (a.vec & VEC_THETA) != 0, vecG = (a.vec & VEC_G) != 0, vecA = (a.vec & VEC_T) != 0;
 
@@ -122,6 +125,13 @@ __global__ __launch_bounds__(kThreads) void k_bwd_block(const BwdArgs a) {
   const int seg = x1 - x0;             // pixels per HR row of the group
   const int spr = (seg + P - 1) / P;   // strips per HR row of the group
 
+  if constexpr (KW == 3) {
+    for (int c = (int)threadIdx.x; c < 81; c += kThreads) {
+      const int oa = c / 9, ob = c - oa * 9;
+      sDec[c] = (uint32_t)((oa / 3) * lx + oa % 3) | ((uint32_t)((ob / 3) * lx + ob % 3) << 8) |
+                ((uint32_t)(oa | (ob << 8)) << 16);
+    }
+  }
   if (a.dalpha) {
     // LR target cells rows qy - r .. qy + r, columns qx0 - r .. qx0 + a.nb - 1 + r,
     // clamped to the LR image (codes from the search never leave it)
@@ -131,15 +141,17 @@ __global__ __launch_bounds__(kThreads) void k_bwd_block(const BwdArgs a) {
       const int cx = min(max(qx0 - r + c, 0), a.w - 1);
       sT[i] = load_cell<T>(TL + (int64_t)cy * a.T_stride + (int64_t)cx * C, C);
     }
-    __syncthreads();
   }
+  if (KW == 3 || a.dalpha) __syncthreads();
 
   // scan lane: one (cell, offset) pair of the group
   const int lane_cell = (int)threadIdx.x / K2;
   const int lane_o = (int)threadIdx.x - lane_cell * K2;
   const bool scanner = a.S && lane_cell < nb;
   const int cx0 = lane_cell * s, cx1 = min(seg, cx0 + s);  // pixel columns of the cell
-  float acc[4] = {0.f, 0.f, 0.f, 0.f};
+  float acc[C];
+#pragma unroll
+  for (int ch = 0; ch < C; ++ch) acc[ch] = 0.f;
 
   for (int yc = y0; yc < y1; yc += a.rows_chunk) {
     const int nrow = min(y1, yc + a.rows_chunk) - yc;
@@ -184,21 +196,36 @@ __global__ __launch_bounds__(kThreads) void k_bwd_block(const BwdArgs a) {
 #pragma unroll
       for (int q = 0; q < P; ++q) {
         const int cdc = min(cd[q], K2 * K2 - 1);
-        const int oa = cdc / K2, ob = cdc - oa * K2;
+        int offa, offb, pair;
+        if constexpr (KW == 3) {
+          const uint32_t e = sDec[cdc];
+          offa = e & 0xff;
+          offb = (e >> 8) & 0xff;
+          pair = e >> 16;
+        } else {
+          const int oa = cdc / K2, ob = cdc - oa * K2;
+          offa = (oa / k) * lx + oa % k;
+          offb = (ob / k) * lx + ob % k;
+          pair = oa | (ob << 8);
+        }
         const int i = ry * pitch + rx + q;
         if (a.S && (full || rx + q < seg)) {
-          sG[i] = make_float4(g[q][0], g[q][1], g[q][2], g[q][3]);
-          sA[i] = al[q];
-          sC[i] = (uint16_t)(oa | (ob << 8));
+          if constexpr (C <= 3) {
+            sG[i] = make_float4(g[q][0], g[q][1], g[q][2], al[q]);
+          } else {
+            sG[i] = make_float4(g[q][0], g[q][1], g[q][2], g[q][3]);
+            sA[i] = al[q];
+          }
+          sC[i] = (uint16_t)pair;
         }
         da[q] = 0.f;
         if (a.dalpha) {
-          const float4 Ta = sT[(oa / k) * lx + cl + oa % k];
-          const float4 Tb = sT[(ob / k) * lx + cl + ob % k];
-          float v = g[q][0] * (Ta.x - Tb.x);
-          v = fmaf(g[q][1], Ta.y - Tb.y, v);
-          v = fmaf(g[q][2], Ta.z - Tb.z, v);
-          v = fmaf(g[q][3], Ta.w - Tb.w, v);
+          const float4 Ta = sT[cl + offa];
+          const float4 Tb = sT[cl + offb];
+          const float dv[4] = {Ta.x - Tb.x, Ta.y - Tb.y, Ta.z - Tb.z, Ta.w - Tb.w};
+          float v = g[q][0] * dv[0];
+#pragma unroll
+          for (int ch = 1; ch < C; ++ch) v = fmaf(g[q][ch], dv[ch], v);
           da[q] = v;
         }
       }
@@ -229,15 +256,14 @@ __global__ __launch_bounds__(kThreads) void k_bwd_block(const BwdArgs a) {
         for (int rx = cx0; rx < cx1; ++rx) {
           const int i = base + rx;
           const int pk = sC[i];
-          const float al = sA[i];
           const float4 g = sG[i];
+          const float al = C <= 3 ? g.w : sA[i];
           const float wa = ((pk & 0xff) == lane_o) ? al : 0.0f;
           const float wb = ((pk >> 8) == lane_o) ? 1.0f - al : 0.0f;
           const float wt = wa + wb;
-          acc[0] = fmaf(wt, g.x, acc[0]);
-          acc[1] = fmaf(wt, g.y, acc[1]);
-          acc[2] = fmaf(wt, g.z, acc[2]);
-          acc[3] = fmaf(wt, g.w, acc[3]);
+          const float gv[4] = {g.x, g.y, g.z, g.w};
+#pragma unroll
+          for (int ch = 0; ch < C; ++ch) acc[ch] = fmaf(wt, gv[ch], acc[ch]);
         }
       }
     }
@@ -247,9 +273,36 @@ __global__ __launch_bounds__(kThreads) void k_bwd_block(const BwdArgs a) {
     const int64_t hw = (int64_t)a.h * a.w;
     float* out = a.S + ((int64_t)lane_o * hw + (int64_t)qy * a.w + qx0 + lane_cell) * C;
 #pragma unroll
-    for (int ch = 0; ch < 4; ++ch)
-      if (ch < C) out[ch] = acc[ch];
+    for (int ch = 0; ch < C; ++ch) out[ch] = acc[ch];
   }
+}
+
+template <typename T, int P, int KW, int C>
+__global__ __launch_bounds__(kThreads) void k_bwd_block(const BwdArgs a) {
+  extern __shared__ float4 smem[];
+  bwd_block<T, P, KW, C>(a, smem);
+}
+
+typedef void (*BwdKernel)(const BwdArgs);
+
+template <typename T, int P, int KW>
+static BwdKernel pick_bwd_c(int C) {
+  switch (C) {
+    case 1: return k_bwd_block<T, P, KW, 1>;
+    case 2: return k_bwd_block<T, P, KW, 2>;
+    case 3: return k_bwd_block<T, P, KW, 3>;
+    default: return k_bwd_block<T, P, KW, 4>;
+  }
+}
+
+template <typename T, int P>
+static BwdKernel pick_bwd_k(int k, int C) {
+  return k == 3 ? pick_bwd_c<T, P, 3>(C) : pick_bwd_c<T, P, 0>(C);
+}
+
+static BwdKernel pick_bwd(bool f16, int P, int k, int C) {
+  if (f16) return P == 4 ? pick_bwd_k<__half, 4>(k, C) : pick_bwd_k<__half, 1>(k, C);
+  return P == 4 ? pick_bwd_k<float, 4>(k, C) : pick_bwd_k<float, 1>(k, C);
 }
 
 __global__ __launch_bounds__(256) void k_bwd_lr(const BwdArgs a) {
@@ -360,20 +413,7 @@ glu_status glu_apply_backward(const glu_theta* theta, const glu_image* T_low, co
   const int64_t groups = (int64_t)h * a.groups_x;
   if (groups > 0x7fffffff) return fail(GLU_ERR_UNSUPPORTED, "image too large");
   hipStream_t sm = (hipStream_t)stream;
-  typedef void (*BwdKernel)(const BwdArgs);
-  const bool f16 = T_low->dtype == GLU_F16, k3 = p->k == 3;
-  BwdKernel kern;
-  if (P == 4) {
-    if (f16)
-      kern = k3 ? k_bwd_block<__half, 4, 3> : k_bwd_block<__half, 4, 0>;
-    else
-      kern = k3 ? k_bwd_block<float, 4, 3> : k_bwd_block<float, 4, 0>;
-  } else {
-    if (f16)
-      kern = k3 ? k_bwd_block<__half, 1, 3> : k_bwd_block<__half, 1, 0>;
-    else
-      kern = k3 ? k_bwd_block<float, 1, 3> : k_bwd_block<float, 1, 0>;
-  }
+  BwdKernel kern = pick_bwd(T_low->dtype == GLU_F16, P, p->k, C);
   hipLaunchKernelGGL(kern, dim3((unsigned)groups), dim3(kThreads), lds, sm, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "backward pass 1 launch");

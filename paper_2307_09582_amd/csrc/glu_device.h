@@ -529,14 +529,13 @@ __device__ __forceinline__ void stage_strip(float4* buf, int lane, int C, const 
 }
 
 // Stores the staged strips of the calling wave.  off = element offset of
-// the lane's own strip in `out`, or -1 when the lane staged nothing; every
-// lane of the wave must call this together.
+// the lane's own strip from `out` (the tile's first element), or -1 when the
+// lane staged nothing; every lane of the wave must call this together.
 template <typename T>
-__device__ __forceinline__ void store_staged(float4* buf, int lane, int C, int64_t off, T* __restrict__ out) {
+__device__ __forceinline__ void store_staged(float4* buf, int lane, int C, int off, T* __restrict__ out) {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  const int lo = (int)(uint32_t)off, hi = (int)(off >> 32);
   const int nw = C == 3 ? 3 : 1;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
@@ -544,7 +543,7 @@ __device__ __forceinline__ void store_staged(float4* buf, int lane, int C, int64
     const int idx = lane + 64 * k;
     const int st = nw == 3 ? idx / 3 : idx;  // strip (owner lane) of the word
     const int part = idx - st * nw;
-    const int64_t o = ((int64_t)__shfl(hi, st, 64) << 32) | (uint32_t)__shfl(lo, st, 64);
+    const int o = __shfl(off, st, 64);
     if (o >= 0) {
       T* dst = out + o + 4 * part;
       if constexpr (sizeof(T) == 4)
@@ -572,6 +571,9 @@ __host__ __device__ constexpr bool uses_pair_table(int mode, int k) { return mod
 // Output staging of the fused search: per wave, 64 strips of 4 pixels of 3
 // float channels (48 bytes each).
 constexpr int kStageWords = (kThreads / 64) * 64 * 3;
+// Fused tiles of windows up to this size map a Theta code to the LDS
+// offsets of its two cells with a table of k^4 entries.
+constexpr int kMaxOffTableK = 5;
 
 // LDS float4 words one search tile needs.
 __host__ __device__ inline int search_tile_words(int tqy, int tqx, int k, int mode, bool fused, bool table) {
@@ -580,6 +582,7 @@ __host__ __device__ inline int search_tile_words(int tqy, int tqx, int k, int mo
   int words = ncell * (fused ? 2 : 1);
   if (mode == MODE_EXH && table) words += 2 * tqy * tqx * (n_pairs(k * k) + 1);
   if (fused) words += kStageWords;
+  if (fused && k <= kMaxOffTableK) words += (k * k * k * k + 3) / 4;
   return words;
 }
 
@@ -626,8 +629,12 @@ __device__ __forceinline__ void search_tile(const ImgDesc& d, int ty, int tx, fl
   const int tstride = n_pairs(K2) + 1;
   const int lane = (int)threadIdx.x & 63;
   // per-wave output staging (fused): after the pair table
-  float4* sStage = smem + (FUSED ? 2 : 1) * ncell +
-                   ((MODE == MODE_EXH && TABLE) ? 2 * tqy * tqx * tstride : 0) + ((int)threadIdx.x >> 6) * 64 * 3;
+  float4* sStageAll = smem + (FUSED ? 2 : 1) * ncell + ((MODE == MODE_EXH && TABLE) ? 2 * tqy * tqx * tstride : 0);
+  float4* sStage = sStageAll + ((int)threadIdx.x >> 6) * 64 * 3;
+  // code -> (offset of cell a) | (offset of cell b) << 16, relative to the
+  // pixel's centre at window offset 0 (fused, k <= kMaxOffTableK)
+  constexpr bool kOffTab = FUSED && KW > 0 && KW <= kMaxOffTableK;
+  uint32_t* sOff = reinterpret_cast<uint32_t*>(sStageAll + kStageWords);
 
   const int rows = tqy * s, cols = tqx * s;
   const int spr = cols / P;
@@ -652,6 +659,12 @@ __device__ __forceinline__ void search_tile(const ImgDesc& d, int ty, int tx, fl
   prefetch(threadIdx.x);
 
   stage_lr<T>(d, qy0, qx0, R, ly, lx, sL, sT);
+  if constexpr (kOffTab) {
+    for (int c = threadIdx.x; c < K2 * K2; c += kThreads) {
+      const int oa = c / K2, ob = c - oa * K2;
+      sOff[c] = (uint32_t)((oa / kw) * lx + oa % kw) | ((uint32_t)((ob / kw) * lx + ob % kw) << 16);
+    }
+  }
   __syncthreads();
   if (MODE == MODE_EXH && TABLE) {
     const int np = n_pairs(K2);
@@ -673,7 +686,8 @@ __device__ __forceinline__ void search_tile(const ImgDesc& d, int ty, int tx, fl
   // then stores 4-element words of consecutive strips, so neighbouring
   // lanes write neighbouring words of a row.  The loop is uniform over a
   // wave for that; lanes past the tile or the image only take part in it.
-  const bool staged = FUSED && P == 4 && vecT && (d.C == 3 || d.C == 1);
+  const bool staged = FUSED && P == 4 && vecT && (d.C == 3 || d.C == 1) &&
+                      (int64_t)rows * d.That_stride < 0x7fffffff;  // tile offsets fit 32 bits
   for (int t = threadIdx.x; t - lane < nstrips; t += kThreads) {
     const int ry = t / spr;
     const int rx = (t - ry * spr) * P;
@@ -686,7 +700,7 @@ __device__ __forceinline__ void search_tile(const ImgDesc& d, int ty, int tx, fl
     prefetch(t + kThreads);
     const bool live = t < nstrips && y < d.H && x < d.W;
     const bool full = interior || (x + P <= d.W);
-    int64_t stage_off = -1;  // element offset of a staged strip in T_hat
+    int stage_off = -1;  // element offset of a staged strip from the tile's first T_hat element
     if (live) {
     const int cy = ry / s, cx = rx / s;
     const LdsWin<KW> win{sL + cy * lx + cx, lx, kw};
@@ -722,9 +736,17 @@ __device__ __forceinline__ void search_tile(const ImgDesc& d, int ty, int tx, fl
       float o[P][4];
 #pragma unroll
       for (int q = 0; q < P; ++q) {
-        const int oa = code[q] / K2, ob = code[q] - oa * K2;
-        const float4 Ta = sT[(cy + oa / kw) * lx + cx + oa % kw];
-        const float4 Tb = sT[(cy + ob / kw) * lx + cx + ob % kw];
+        float4 Ta, Tb;
+        if constexpr (kOffTab) {
+          const uint32_t pk = sOff[code[q]];
+          const float4* base = sT + cy * lx + cx;
+          Ta = base[pk & 0xffff];
+          Tb = base[pk >> 16];
+        } else {
+          const int oa = code[q] / K2, ob = code[q] - oa * K2;
+          Ta = sT[(cy + oa / kw) * lx + cx + oa % kw];
+          Tb = sT[(cy + ob / kw) * lx + cx + ob % kw];
+        }
         o[q][0] = fmaf(al[q], Ta.x - Tb.x, Tb.x);
         o[q][1] = fmaf(al[q], Ta.y - Tb.y, Tb.y);
         o[q][2] = fmaf(al[q], Ta.z - Tb.z, Tb.z);
@@ -732,13 +754,15 @@ __device__ __forceinline__ void search_tile(const ImgDesc& d, int ty, int tx, fl
       }
       if (staged && full) {
         stage_strip<T, P>(sStage, lane, d.C, o);
-        stage_off = (int64_t)y * d.That_stride + (int64_t)x * d.C;
+        stage_off = (int)((int64_t)ry * d.That_stride + (int64_t)rx * d.C);
       } else {
         store_out<T, P>(static_cast<T*>(d.That) + (int64_t)y * d.That_stride, x, d.W, d.C, vecT, full, o);
       }
     }
     }  // live
-    if (staged) store_staged<T>(sStage, lane, d.C, stage_off, static_cast<T*>(d.That));
+    if (staged)
+      store_staged<T>(sStage, lane, d.C, stage_off,
+                      static_cast<T*>(d.That) + (int64_t)qy0 * s * d.That_stride + (int64_t)qx0 * s * d.C);
   }
 }
 
