@@ -305,26 +305,40 @@ static BwdKernel pick_bwd(bool f16, int P, int k, int C) {
   return P == 4 ? pick_bwd_k<float, 4>(k, C) : pick_bwd_k<float, 1>(k, C);
 }
 
+template <int KW, int C>
 __global__ __launch_bounds__(256) void k_bwd_lr(const BwdArgs a) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t hw = (int64_t)a.h * a.w;
   if (q >= hw) return;
   const int qy = (int)(q / a.w), qx = (int)(q - (int64_t)qy * a.w);
-  const int k = a.k, r = k / 2, K2 = k * k, C = a.C;
-  float acc[4] = {0.f, 0.f, 0.f, 0.f};
+  const int k = KW > 0 ? KW : a.k;
+  const int r = k / 2, K2 = k * k;
+  float acc[C];
+#pragma unroll
+  for (int ch = 0; ch < C; ++ch) acc[ch] = 0.f;
+  constexpr int kUnroll = KW > 0 ? KW * KW : 1;
+#pragma unroll kUnroll
   for (int o = 0; o < K2; ++o) {
     // the cell c whose window offset o points at q: c = q - (o / k - r, o % k - r)
     const int cy = qy - (o / k - r), cx = qx - (o % k - r);
-    if (cy < 0 || cy >= a.h || cx < 0 || cx >= a.w) continue;
-    const float* src = a.S + ((int64_t)o * hw + (int64_t)cy * a.w + cx) * C;
+    const bool in = cy >= 0 && cy < a.h && cx >= 0 && cx < a.w;
+    const float* src = a.S + ((int64_t)o * hw + (in ? (int64_t)cy * a.w + cx : 0)) * C;
 #pragma unroll
-    for (int ch = 0; ch < 4; ++ch)
-      if (ch < C) acc[ch] += src[ch];
+    for (int ch = 0; ch < C; ++ch) acc[ch] += in ? src[ch] : 0.0f;
   }
   float* out = a.dT + (int64_t)qy * a.dT_stride + (int64_t)qx * C;
 #pragma unroll
-  for (int ch = 0; ch < 4; ++ch)
-    if (ch < C) out[ch] = acc[ch];
+  for (int ch = 0; ch < C; ++ch) out[ch] = acc[ch];
+}
+
+template <int KW>
+static BwdKernel pick_lr_c(int C) {
+  switch (C) {
+    case 1: return k_bwd_lr<KW, 1>;
+    case 2: return k_bwd_lr<KW, 2>;
+    case 3: return k_bwd_lr<KW, 3>;
+    default: return k_bwd_lr<KW, 4>;
+  }
 }
 
 // Cells per workgroup (one scan lane per (cell, offset)) and HR rows per
@@ -419,7 +433,8 @@ glu_status glu_apply_backward(const glu_theta* theta, const glu_image* T_low, co
   if (e != hipSuccess) return hip_fail(e, "backward pass 1 launch");
   if (grad_T_low) {
     const int64_t n = (int64_t)h * w;
-    hipLaunchKernelGGL(k_bwd_lr, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, sm, a);
+    BwdKernel lr = p->k == 3 ? pick_lr_c<3>(C) : pick_lr_c<0>(C);
+    hipLaunchKernelGGL(lr, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, sm, a);
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "backward pass 2 launch");
   }
