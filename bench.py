@@ -112,6 +112,38 @@ def _events_ms(torch, stream, fn, steps, warmup):
     return e0.elapsed_time(e1) / steps
 
 
+def _per_launch_us(torch, stream, fn, n, warmup):
+    """Median, p10 and p90 of n single launches, each bracketed by its own
+    pair of HIP events on `stream` (launches still queue back to back)."""
+    for i in range(warmup):
+        fn(i)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
+    for i, (a, b) in enumerate(ev):
+        a.record(stream)
+        fn(i)
+        b.record(stream)
+    torch.cuda.synchronize()
+    t = sorted(1e3 * a.elapsed_time(b) for a, b in ev)
+    return {"median": round(t[n // 2], 2), "p10": round(t[n // 10], 2), "p90": round(t[(9 * n) // 10], 2)}
+
+
+def _lr_f2_torch(torch, c):
+    """LR operator f2 (5x5 Gaussian blur, sigma 1, edge-replicate, then the
+    colour matrix) on the GPU in float32."""
+    import synth
+
+    x = torch.arange(-2, 3, dtype=torch.float32, device=c.device)
+    g = torch.exp(-(x * x) / 2.0)
+    k = torch.outer(g, g)
+    k = (k / k.sum()).reshape(1, 1, 5, 5).repeat(3, 1, 1, 1)
+    img = c.float().permute(2, 0, 1).unsqueeze(0)
+    img = torch.nn.functional.pad(img, (2, 2, 2, 2), mode="replicate")
+    blur = torch.nn.functional.conv2d(img, k, groups=3)[0].permute(1, 2, 0)
+    M = torch.tensor(synth.COLOR_MATRIX, dtype=torch.float32, device=c.device)
+    return (blur @ M.T).contiguous()
+
+
 def _lr_f1_torch(torch, c):
     """LR operator f1 (colour matrix, then gamma 0.8) on the GPU in float32."""
     import synth
@@ -207,6 +239,8 @@ def main():
     value = n_px / (ms_step * 1e-3) / 1e6
     print("headline done: %.2f us/step" % (1e3 * ms_step), file=sys.stderr, flush=True)
 
+    dist = _per_launch_us(torch, stream, step, 200, 20) if args.only == "all" else None
+
     kern = {}
     other = "fast" if args.mode == "exhaustive" else "exhaustive"
     if args.only == "all":
@@ -291,6 +325,7 @@ def main():
         },
         "roofline": roof,
         "cpu_baseline": cpu,
+        "step_us_per_launch": dist,
         "kernels_us": {m: {k2: round(v, 2) for k2, v in d.items()} for m, d in kern.items()},
         "bwd": bwd,
         "configs": configs,
@@ -348,8 +383,14 @@ def _configs(np, torch, synth, glu, dev, stream, scene):
                                                          workspace=jws)
             torch.cuda.synchronize()
             walls.append(time.perf_counter() - t)
+        Tj = _lr_f2_torch(torch, Lj)
+        oj = torch.empty_like(I)
+        thj2 = glu.empty_theta(2048, 2048, dev)
+        ms_sa = _events_ms(torch, stream, lambda i: glu.search_apply(I, Lj, Tj, 8, 3, EPS, mode, theta=thj2, out=oj),
+                           100, 10)
         r[mode] = {
             "wall_ms": round(1e3 * sorted(walls)[1], 3),
+            "search_apply_after_us": round(1e3 * ms_sa, 2),
             "Mpx_s": round(2048 * 2048 / sorted(walls)[1] / 1e6, 1),
             "rounds_run": stats["rounds_run"],
             "n_large": stats["n_large"][: stats["rounds_run"]],
@@ -378,9 +419,17 @@ def _configs(np, torch, synth, glu, dev, stream, scene):
         g = plan.capture_graph()
         ms = _events_ms(torch, stream, lambda i: g.replay(), 10, 2)
         ms_launch = _events_ms(torch, stream, lambda i: plan.launch(), 10, 2)
+
+        def per_frame(i):
+            for it in items:
+                glu.search_apply(it["I"], it["I_low"], it["T_low"], S, K, EPS, mode, store_theta=False,
+                                 out=it["T_hat"])
+
+        ms_loop = _events_ms(torch, stream, per_frame, 5, 1)
         npx = 60 * H * W
         r[mode] = {"graph_ms": round(ms, 3), "Mpx_s": round(npx / (ms * 1e-3) / 1e6, 1),
                    "frames_per_s": round(60 / (ms * 1e-3), 1), "launch_ms": round(ms_launch, 3),
+                   "per_frame_loop_ms": round(ms_loop, 3),
                    "hbm_frac": round(12 * npx / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
         del g
         plan.close()
@@ -416,7 +465,15 @@ def _configs(np, torch, synth, glu, dev, stream, scene):
                 tuned["s%d_k%d" % key] = glu.autotune(it, mode=mode)
         plan = glu.BatchPlan(items, mode=mode)
         ms = _events_ms(torch, stream, lambda i: plan.launch(), 5, 1)
+
+        def per_image(i):
+            for it in items:
+                glu.search_apply(it["I"], it["I_low"], it["T_low"], it["s"], it["k"], EPS, mode, store_theta=False,
+                                 out=it["T_hat"])
+
+        ms_loop = _events_ms(torch, stream, per_image, 3, 1)
         r[mode] = {"ms": round(ms, 3), "Mpx_s": round(npx / (ms * 1e-3) / 1e6, 1), "tile_variants": tuned,
+                   "per_image_loop_ms": round(ms_loop, 3),
                    "hbm_frac": round(24 * npx / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
         plan.close()
     out["uneven_64"] = dict(r, n_images=len(specs), Mpx=round(npx / 1e6, 1))
@@ -444,8 +501,17 @@ def _configs(np, torch, synth, glu, dev, stream, scene):
             glu.apply_backward(thb, Tb, G, 8, 3, workspace=ws, out_T_low=gT, out_alpha=ga)
 
     ms = _events_ms(torch, stream, bwd_batch, 20, 3)
+    outs = [torch.empty((1024, 1024, 3), device=dev) for _ in bat]
+
+    def fwd_bwd_batch(i):
+        for (thb, Tb, G, gT, ga), ob in zip(bat, outs):
+            glu.apply(thb, Tb, 8, 3, out=ob)
+            glu.apply_backward(thb, Tb, G, 8, 3, workspace=ws, out_T_low=gT, out_alpha=ga)
+
+    ms_fb = _events_ms(torch, stream, fwd_bwd_batch, 20, 3)
     npx = 16 * 1024 * 1024
     out["bwd_16x1024"] = {"ms": round(ms, 4), "Mpx_s": round(npx / (ms * 1e-3) / 1e6, 1),
+                          "fwd_bwd_ms": round(ms_fb, 4),
                           "hbm_frac": round(BYTES_PER_PX["bwd"] * npx / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     print("bwd batch done", file=sys.stderr, flush=True)
     return out

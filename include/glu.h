@@ -253,14 +253,19 @@ glu_status glu_joint_downsample(const glu_image* I, glu_image* I_low, const glu_
 
 /* ---------------------------------------------------------------------------
  * Batched persistent execution: search + apply of many images or frames of
- * any mix of sizes, ratios s and windows k in ONE kernel launch.
+ * any mix of sizes, ratios s, windows k and storage types.  The items are
+ * grouped by kernel variant (window 3, 5 or other; 4 or 1 pixels per strip,
+ * i.e. 4 | s or not; float32 or float16): each group runs in ONE persistent
+ * launch of a kernel specialised for it, so a batch of one variant (the
+ * frames of a video) is a single launch and a mixed batch one launch per
+ * variant present, enqueued back to back on the stream.
  *
  * glu_batch_plan_create validates every item (same rules as
  * glu_search_apply, with the item's own s and k; eps and mode from p),
  * picks a tile shape per item (from the autotune cache when present, see
  * glu_autotune), builds a device descriptor table and copies it once.  It
  * allocates that table and synchronises.  The plan owns its device memory.
- * glu_batch_plan_launch enqueues the single persistent launch; it performs no
+ * glu_batch_plan_launch enqueues the plan's launches; it performs no
  * allocation, copy or memset, so it can be captured into a hipGraph.
  * Item buffers must stay valid for every launch of the plan.
  * ------------------------------------------------------------------------- */
@@ -280,7 +285,8 @@ glu_status glu_batch_plan_create(const glu_batch_item* items /* HOST */, int32_t
                                  const glu_params* p, glu_batch_plan** out /* HOST */);
 glu_status glu_batch_plan_launch(const glu_batch_plan* plan, void* stream);
 void glu_batch_plan_destroy(glu_batch_plan* plan);
-/* Number of tiles and workgroups of a plan (HOST ints, nullable). */
+/* Number of tiles and of workgroups over all launches of a plan (HOST ints,
+ * nullable). */
 glu_status glu_batch_plan_info(const glu_batch_plan* plan, int64_t* n_tiles, int32_t* n_groups);
 
 /* ---------------------------------------------------------------------------

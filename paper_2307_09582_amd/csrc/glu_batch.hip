@@ -1,14 +1,20 @@
 // Batched persistent execution and the tile autotuner.
 //
 // A plan holds a device table of image descriptors (any mix of sizes,
-// ratios s, windows k and storage types) with the prefix sum of their tile
-// counts.  One launch of a persistent kernel runs fused search + apply over
-// all of them: workgroup g takes global tiles g, g + G, g + 2G, ... (G =
-// number of workgroups), finds the image of a tile by binary search over the
-// prefix sums and runs the same per-tile device code as the single-image
-// path, so every pixel gets bitwise the same result as a single-image launch
-// with the same tile shape.  The launch does no allocation, copy or memset,
-// so it can be captured into a hipGraph and replayed.
+// ratios s, windows k and storage types), grouped by kernel variant (window
+// class, pixels per strip, storage type), each group with the prefix sum of
+// its tile counts.  One launch of a kernel specialised for the group's
+// variant runs fused search + apply over all of the group's images, one
+// workgroup per tile: workgroup g finds the image of tile g by binary search
+// over the prefix sums and runs the same per-tile device code as the
+// single-image path, so every pixel gets bitwise the same result as a
+// single-image launch with the same tile shape.  A batch of one variant
+// (frames of a video) is one launch; a mixed batch is one launch per
+// variant, enqueued back to back.  One kernel holding every variant would
+// carry the register allocation of the largest one, and a persistent loop
+// over tiles keeps values live across iterations; both cost occupancy.
+// Launching does no allocation, copy or memset, so it can be captured into
+// a hipGraph and replayed.
 //
 // The autotuner times the candidate tile shapes of one (mode, k, s, dtype)
 // configuration on a real workload and records the fastest in a
@@ -54,58 +60,77 @@ struct BatchTable {
   const ImgDesc* items;
   int32_t n_items;
   int64_t n_tiles;
+  int64_t tile0;  // first tile of this launch (launches of at most kMaxGrid tiles)
   float eps;
 };
 
-template <int MODE>
-__device__ __forceinline__ void run_tile(const ImgDesc& d, int ty, int tx, float eps, float4* smem) {
-  const int v = d.variant;  // ((kwclass * 2 + pclass) * 2 + mode) * 2 + dtype
-  const int dt = v & 1, pc = (v >> 2) & 1, kc = v >> 3;
-  if (kc == 0) {
-    if (pc == 0) {
-      if (dt == 0) search_tile<3, 4, MODE, float, true, MODE == MODE_EXH>(d, ty, tx, eps, smem);
-      else search_tile<3, 4, MODE, __half, true, MODE == MODE_EXH>(d, ty, tx, eps, smem);
-    } else {
-      if (dt == 0) search_tile<3, 1, MODE, float, true, MODE == MODE_EXH>(d, ty, tx, eps, smem);
-      else search_tile<3, 1, MODE, __half, true, MODE == MODE_EXH>(d, ty, tx, eps, smem);
-    }
-  } else if (kc == 1) {
-    if (pc == 0) {
-      if (dt == 0) search_tile<5, 4, MODE, float, true, false>(d, ty, tx, eps, smem);
-      else search_tile<5, 4, MODE, __half, true, false>(d, ty, tx, eps, smem);
-    } else {
-      if (dt == 0) search_tile<5, 1, MODE, float, true, false>(d, ty, tx, eps, smem);
-      else search_tile<5, 1, MODE, __half, true, false>(d, ty, tx, eps, smem);
-    }
-  } else {
-    if (pc == 0) {
-      if (dt == 0) search_tile<0, 4, MODE, float, true, false>(d, ty, tx, eps, smem);
-      else search_tile<0, 4, MODE, __half, true, false>(d, ty, tx, eps, smem);
-    } else {
-      if (dt == 0) search_tile<0, 1, MODE, float, true, false>(d, ty, tx, eps, smem);
-      else search_tile<0, 1, MODE, __half, true, false>(d, ty, tx, eps, smem);
-    }
-  }
+constexpr int64_t kMaxGrid = int64_t(1) << 30;
+
+__device__ __forceinline__ int64_t uniform_i64(int64_t v) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
-template <int MODE>
+template <int MODE, int KW, int P, typename T>
 __global__ __launch_bounds__(kThreads) void k_batch(const BatchTable tab) {
   extern __shared__ float4 smem[];
-  for (int64_t t = blockIdx.x; t < tab.n_tiles; t += gridDim.x) {
+  {
+    const int64_t t = tab.tile0 + blockIdx.x;
+    if (t >= tab.n_tiles) return;
     // image of tile t: last item with tile_begin <= t
     int lo = 0, hi = tab.n_items - 1;
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
-      if (tab.items[mid].tile_begin <= t) lo = mid;
+      if (uniform_i64(tab.items[mid].tile_begin) <= t) lo = mid;
       else hi = mid - 1;
     }
-    const ImgDesc d = tab.items[lo];
+    // the descriptor is the same for the whole workgroup: read it through
+    // readfirstlane so that it lives in scalar registers, as kernel
+    // arguments do in the single-image launch
+    ImgDesc d;
+    {
+      constexpr int NW = (int)(sizeof(ImgDesc) / 4);
+      const uint32_t* src = reinterpret_cast<const uint32_t*>(tab.items + lo);
+      uint32_t w[NW];
+#pragma unroll
+      for (int i = 0; i < NW; ++i) w[i] = (uint32_t)__builtin_amdgcn_readfirstlane((int)src[i]);
+      __builtin_memcpy(&d, w, sizeof(ImgDesc));
+    }
     const int64_t local = t - d.tile_begin;
     const int ty = (int)(local / d.tiles_x), tx = (int)(local - (int64_t)ty * d.tiles_x);
-    run_tile<MODE>(d, ty, tx, tab.eps, smem);
-    __syncthreads();  // the next tile restages LDS
+    search_tile<KW, P, MODE, T, true, uses_pair_table(MODE, KW)>(d, ty, tx, tab.eps, smem);
   }
 }
+
+typedef void (*BatchKernel)(const BatchTable);
+
+template <int MODE, int KW>
+static BatchKernel pick_batch_kw(int P, int dtype) {
+  if (P == 4) return dtype == GLU_F16 ? k_batch<MODE, KW, 4, __half> : k_batch<MODE, KW, 4, float>;
+  return dtype == GLU_F16 ? k_batch<MODE, KW, 1, __half> : k_batch<MODE, KW, 1, float>;
+}
+
+template <int MODE>
+static BatchKernel pick_batch_m(int k, int P, int dtype) {
+  if (k == 3) return pick_batch_kw<MODE, 3>(P, dtype);
+  if (k == 5) return pick_batch_kw<MODE, 5>(P, dtype);
+  return pick_batch_kw<MODE, 0>(P, dtype);
+}
+
+static BatchKernel pick_batch(int mode, int k, int P, int dtype) {
+  return mode == MODE_EXH ? pick_batch_m<MODE_EXH>(k, P, dtype) : pick_batch_m<MODE_FAST>(k, P, dtype);
+}
+
+// One launch of a plan: the images of one kernel variant.
+struct BatchGroup {
+  BatchKernel kern;
+  int32_t first;    // first descriptor of the group in the device table
+  int32_t n_items;
+  int64_t n_tiles;
+  int32_t n_wgs;    // workgroups of the group (one per tile, capped at kMaxGrid)
+  size_t lds;       // dynamic LDS bytes (largest tile of the group)
+};
 
 }  // namespace glu
 
@@ -115,8 +140,8 @@ struct glu_batch_plan {
   ImgDesc* d_items = nullptr;
   int32_t n_items = 0;
   int64_t n_tiles = 0;
-  int32_t n_groups = 0;
-  size_t lds = 0;
+  int32_t n_groups = 0;  // workgroups over all launches
+  std::vector<glu::BatchGroup> groups;
   int mode = 0;
   float eps = 0.f;
 };
@@ -189,10 +214,9 @@ static glu_status plan_build(const glu_batch_item* items, int32_t n, const glu_p
   base.k = 3;
   if ((st = check_params(&base))) return st;
   const int mode = p->mode == GLU_SEARCH_FAST ? MODE_FAST : MODE_EXH;
-  std::vector<ImgDesc> host;
-  host.reserve(n);
-  size_t lds = 16;
-  int64_t tiles = 0;
+  std::vector<ImgDesc> all;
+  std::vector<size_t> all_lds;
+  all.reserve(n);
   for (int i = 0; i < n; ++i) {
     ImgDesc d;
     size_t l;
@@ -200,16 +224,38 @@ static glu_status plan_build(const glu_batch_item* items, int32_t n, const glu_p
       return fail(st, "item %d: %s", i, glu_last_error());
     }
     if ((int64_t)d.H * d.W == 0) continue;
-    d.tile_begin = tiles;
-    tiles += (int64_t)d.tiles_x * d.tiles_y;
-    lds = std::max(lds, l);
+    all.push_back(d);
+    all_lds.push_back(l);
+  }
+  // group by kernel variant, keeping the items' order inside a group
+  std::vector<int> order(all.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return all[a].variant < all[b].variant; });
+  std::vector<ImgDesc> host;
+  host.reserve(all.size());
+  std::vector<BatchGroup> groups;
+  int64_t tiles_total = 0;
+  for (size_t j = 0; j < order.size(); ++j) {
+    ImgDesc d = all[order[j]];
+    if (groups.empty() || host.back().variant != d.variant) {
+      BatchGroup g{};
+      g.kern = pick_batch(mode, d.k, (d.s % 4 == 0) ? 4 : 1, d.dtype);
+      g.first = (int32_t)host.size();
+      g.lds = 16;
+      groups.push_back(g);
+    }
+    BatchGroup& g = groups.back();
+    d.tile_begin = g.n_tiles;
+    g.n_tiles += (int64_t)d.tiles_x * d.tiles_y;
+    g.n_items += 1;
+    g.lds = std::max(g.lds, all_lds[order[j]]);
+    tiles_total += (int64_t)d.tiles_x * d.tiles_y;
     host.push_back(d);
   }
   glu_batch_plan* plan = new (std::nothrow) glu_batch_plan();
   if (!plan) return fail(GLU_ERR_NOMEM, "plan");
   plan->n_items = (int32_t)host.size();
-  plan->n_tiles = tiles;
-  plan->lds = lds;
+  plan->n_tiles = tiles_total;
   plan->mode = mode;
   plan->eps = p->eps;
   if (!host.empty()) {
@@ -224,33 +270,34 @@ static glu_status plan_build(const glu_batch_item* items, int32_t n, const glu_p
       delete plan;
       return hip_fail(e, "descriptor upload");
     }
-    int dev = 0, cus = 0, per_cu = 0;
-    hipGetDevice(&dev);
-    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    const void* kern = mode == MODE_EXH ? (const void*)k_batch<MODE_EXH> : (const void*)k_batch<MODE_FAST>;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kThreads, lds);
-    if (e != hipSuccess || per_cu < 1) per_cu = 1;
-    const int64_t want = (int64_t)std::max(1, cus) * per_cu;
-    plan->n_groups = (int32_t)std::max<int64_t>(1, std::min<int64_t>(want, tiles));
+    int64_t wgs = 0;
+    for (BatchGroup& g : groups) {
+      g.n_wgs = (int32_t)std::min<int64_t>(g.n_tiles, kMaxGrid);
+      wgs += g.n_tiles;
+    }
+    plan->n_groups = (int32_t)std::min<int64_t>(wgs, 0x7fffffff);
   }
+  plan->groups = std::move(groups);
   *out = plan;
   return GLU_OK;
 }
 
 static glu_status plan_launch(const glu_batch_plan* plan, void* stream) {
   if (!plan) return fail(GLU_ERR_NULL, "plan is NULL");
-  if (plan->n_tiles == 0) return GLU_OK;
-  BatchTable t;
-  t.items = plan->d_items;
-  t.n_items = plan->n_items;
-  t.n_tiles = plan->n_tiles;
-  t.eps = plan->eps;
-  if (plan->mode == MODE_EXH)
-    hipLaunchKernelGGL(k_batch<MODE_EXH>, dim3(plan->n_groups), dim3(kThreads), plan->lds, (hipStream_t)stream, t);
-  else
-    hipLaunchKernelGGL(k_batch<MODE_FAST>, dim3(plan->n_groups), dim3(kThreads), plan->lds, (hipStream_t)stream, t);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return hip_fail(e, "batch launch");
+  for (const BatchGroup& g : plan->groups) {
+    for (int64_t t0 = 0; t0 < g.n_tiles; t0 += kMaxGrid) {
+      BatchTable t;
+      t.items = plan->d_items + g.first;
+      t.n_items = g.n_items;
+      t.n_tiles = g.n_tiles;
+      t.tile0 = t0;
+      t.eps = plan->eps;
+      const unsigned grid = (unsigned)std::min<int64_t>(g.n_tiles - t0, kMaxGrid);
+      hipLaunchKernelGGL(g.kern, dim3(grid), dim3(kThreads), g.lds, (hipStream_t)stream, t);
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return hip_fail(e, "batch launch");
+    }
+  }
   return GLU_OK;
 }
 
