@@ -481,37 +481,45 @@ def _configs(np, torch, synth, glu, dev, stream, scene):
     torch.cuda.synchronize()
     print("uneven done", file=sys.stderr, flush=True)
 
-    # backward over a batch of 16 x 1024 x 1024, x8, Theta from the search
+    # backward over a batch of 16 x 1024 x 1024, x8, Theta from the search:
+    # one batched call (one launch per pass), and 16 single-image calls
     canvas = torch.from_numpy(scene.canvas.astype(np.float32)).to(dev)
-    bat = []
-    gen = torch.Generator(dev)
-    gen.manual_seed(16)
-    for b in range(16):
-        Ib = _noisy_crop(torch, canvas, (b % 2) * 1000, (b // 2) * 370, 1024, 1024, 8000 + b, torch.float32)
+    B5, N5 = 16, 1024
+    code5 = torch.empty((B5, N5, N5), dtype=torch.int16, device=dev)
+    alpha5 = torch.empty((B5, N5, N5), dtype=torch.float32, device=dev)
+    T5 = torch.empty((B5, N5 // 8, N5 // 8, 3), dtype=torch.float32, device=dev)
+    for b in range(B5):
+        Ib = _noisy_crop(torch, canvas, (b % 2) * 1000, (b // 2) * 370, N5, N5, 8000 + b, torch.float32)
         Ilb = glu.downsample(Ib, 8, "point")
-        Tb = _lr_f1_torch(torch, Ilb).contiguous()
-        thb = glu.search(Ib, Ilb, 8, 3, EPS)
-        G = torch.randn((1024, 1024, 3), generator=gen, device=dev)
-        bat.append((thb, Tb, G, torch.empty_like(Tb), torch.empty((1024, 1024), device=dev)))
+        T5[b] = _lr_f1_torch(torch, Ilb)
+        glu.search(Ib, Ilb, 8, 3, EPS, theta=glu.Theta(code5[b], alpha5[b]))
     del canvas
-    ws = torch.empty(glu.apply_backward_workspace(1024, 1024, 3, 8, 3) // 4 + 1, device=dev)
+    th5 = glu.Theta(code5, alpha5)
+    G5 = torch.randn((B5, N5, N5, 3), generator=torch.Generator(dev).manual_seed(16), device=dev)
+    gT5 = torch.empty_like(T5)
+    ga5 = torch.empty((B5, N5, N5), device=dev)
+    out5 = torch.empty((B5, N5, N5, 3), device=dev)
+    ws5 = torch.empty(glu.apply_backward_batched_workspace(B5, N5, N5, 3, 8, 3) // 4 + 1, device=dev)
+    ws1 = torch.empty(glu.apply_backward_workspace(N5, N5, 3, 8, 3) // 4 + 1, device=dev)
 
-    def bwd_batch(i):
-        for thb, Tb, G, gT, ga in bat:
-            glu.apply_backward(thb, Tb, G, 8, 3, workspace=ws, out_T_low=gT, out_alpha=ga)
+    def bwd_batched(i):
+        glu.apply_backward(th5, T5, G5, 8, 3, workspace=ws5, out_T_low=gT5, out_alpha=ga5)
 
-    ms = _events_ms(torch, stream, bwd_batch, 20, 3)
-    outs = [torch.empty((1024, 1024, 3), device=dev) for _ in bat]
+    def fwd_bwd_batched(i):
+        glu.apply(th5, T5, 8, 3, out=out5)
+        glu.apply_backward(th5, T5, G5, 8, 3, workspace=ws5, out_T_low=gT5, out_alpha=ga5)
 
-    def fwd_bwd_batch(i):
-        for (thb, Tb, G, gT, ga), ob in zip(bat, outs):
-            glu.apply(thb, Tb, 8, 3, out=ob)
-            glu.apply_backward(thb, Tb, G, 8, 3, workspace=ws, out_T_low=gT, out_alpha=ga)
+    def bwd_per_image(i):
+        for b in range(B5):
+            glu.apply_backward(glu.Theta(code5[b], alpha5[b]), T5[b], G5[b], 8, 3, workspace=ws1, out_T_low=gT5[b],
+                               out_alpha=ga5[b])
 
-    ms_fb = _events_ms(torch, stream, fwd_bwd_batch, 20, 3)
-    npx = 16 * 1024 * 1024
+    ms = _events_ms(torch, stream, bwd_batched, 50, 5)
+    ms_fb = _events_ms(torch, stream, fwd_bwd_batched, 50, 5)
+    ms_loop = _events_ms(torch, stream, bwd_per_image, 20, 3)
+    npx = B5 * N5 * N5
     out["bwd_16x1024"] = {"ms": round(ms, 4), "Mpx_s": round(npx / (ms * 1e-3) / 1e6, 1),
-                          "fwd_bwd_ms": round(ms_fb, 4),
+                          "fwd_bwd_ms": round(ms_fb, 4), "per_image_calls_ms": round(ms_loop, 4),
                           "hbm_frac": round(BYTES_PER_PX["bwd"] * npx / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     print("bwd batch done", file=sys.stderr, flush=True)
     return out

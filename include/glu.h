@@ -167,6 +167,25 @@ glu_status glu_apply(const glu_theta* theta, const glu_image* T_low, const glu_p
                      glu_image* T_hat, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * Batches of n images of one size (H, W, C, dtype, s, k shared) in one
+ * launch: image b of each buffer starts at the descriptor's pointer plus b
+ * times the buffer's batch stride, in elements of that buffer.  Row strides
+ * are the descriptors'.  Output images of a batch must not overlap.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  int64_t theta;       /* code and alpha planes                              */
+  int64_t T_low;
+  int64_t T_hat;       /* T_hat (glu_apply_batched) or grad_T_hat (backward) */
+  int64_t grad_T_low;
+  int64_t grad_alpha;
+} glu_batch_strides;
+
+/* glu_apply over n images in one launch (n in 0..65535; strides may be
+ * NULL when n <= 1).  Results are bitwise those of n glu_apply calls. */
+glu_status glu_apply_batched(int32_t n, const glu_batch_strides* strides, const glu_theta* theta,
+                             const glu_image* T_low, const glu_params* p, glu_image* T_hat, void* stream);
+
+/* ---------------------------------------------------------------------------
  * glu_search_apply - glu_search followed by glu_apply in one pass over the
  * HR image (Algorithm 1 computes T_hat_p right after Theta_p).
  *
@@ -204,6 +223,16 @@ size_t glu_apply_backward_workspace(int32_t H, int32_t W, int32_t C, const glu_p
 glu_status glu_apply_backward(const glu_theta* theta, const glu_image* T_low, const glu_params* p,
                               const glu_image* grad_T_hat, glu_image* grad_T_low,
                               float* grad_alpha, void* workspace, size_t ws_bytes, void* stream);
+
+/* glu_apply_backward over n images of one size in one launch per pass
+ * (strides as for glu_apply_batched, with strides->T_hat the batch stride of
+ * grad_T_hat; may be NULL when n <= 1).  The workspace holds one image's
+ * workspace per image.  Results are bitwise those of n separate calls. */
+size_t glu_apply_backward_batched_workspace(int32_t n, int32_t H, int32_t W, int32_t C, const glu_params* p);
+glu_status glu_apply_backward_batched(int32_t n, const glu_batch_strides* strides, const glu_theta* theta,
+                                      const glu_image* T_low, const glu_params* p,
+                                      const glu_image* grad_T_hat, glu_image* grad_T_low,
+                                      float* grad_alpha, void* workspace, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
  * glu_downsample - initial LR guide (not on the timed path).

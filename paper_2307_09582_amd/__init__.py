@@ -17,6 +17,7 @@ from .glu import (  # noqa: F401
     apply,
     apply_backward,
     apply_backward_workspace,
+    apply_backward_batched_workspace,
     downsample,
     empty_theta,
     glu_apply_autograd,

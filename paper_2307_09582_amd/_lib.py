@@ -95,6 +95,16 @@ class glu_jd_log(C.Structure):
     ]
 
 
+class glu_batch_strides(C.Structure):
+    _fields_ = [
+        ("theta", C.c_int64),
+        ("T_low", C.c_int64),
+        ("T_hat", C.c_int64),
+        ("grad_T_low", C.c_int64),
+        ("grad_alpha", C.c_int64),
+    ]
+
+
 class glu_batch_item(C.Structure):
     _fields_ = [
         ("I", glu_image),
@@ -111,6 +121,16 @@ P = C.POINTER
 _SIGS = {
     "glu_search": (C.c_int, [P(glu_image), P(glu_image), P(glu_params), P(glu_theta), C.c_void_p, C.c_void_p]),
     "glu_apply": (C.c_int, [P(glu_theta), P(glu_image), P(glu_params), P(glu_image), C.c_void_p]),
+    "glu_apply_batched": (
+        C.c_int,
+        [C.c_int32, P(glu_batch_strides), P(glu_theta), P(glu_image), P(glu_params), P(glu_image), C.c_void_p],
+    ),
+    "glu_apply_backward_batched_workspace": (C.c_size_t, [C.c_int32, C.c_int32, C.c_int32, C.c_int32, P(glu_params)]),
+    "glu_apply_backward_batched": (
+        C.c_int,
+        [C.c_int32, P(glu_batch_strides), P(glu_theta), P(glu_image), P(glu_params), P(glu_image), P(glu_image),
+         C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p],
+    ),
     "glu_search_apply": (
         C.c_int,
         [P(glu_image), P(glu_image), P(glu_image), P(glu_params), P(glu_theta), C.c_void_p, P(glu_image), C.c_void_p],

@@ -133,10 +133,21 @@ __global__ __launch_bounds__(kThreads) void k_search(const ImgDesc d, float eps)
   search_tile<KW, P, MODE, T, FUSED, uses_pair_table(MODE, KW)>(d, ty, tx, eps, smem);
 }
 
-// One workgroup per tile of one LR row by d.tqx LR columns.
+// One workgroup per tile of one LR row by d.tqx LR columns; blockIdx.y is
+// the image of a batch (element offsets per image in `off`).
+struct ApplyBatch {
+  int64_t theta, T_low, T_hat;
+};
+
 template <int KW, int P, typename T>
-__global__ __launch_bounds__(kThreads) void k_apply(const ImgDesc d, uint32_t s_magic) {
+__global__ __launch_bounds__(kThreads) void k_apply(const ImgDesc d0, uint32_t s_magic, const ApplyBatch off) {
   extern __shared__ float4 smem[];
+  ImgDesc d = d0;
+  const int64_t b = blockIdx.y;
+  d.code += b * off.theta;
+  d.alpha += b * off.theta;
+  d.T = static_cast<const T*>(d0.T) + b * off.T_low;
+  d.That = static_cast<T*>(d0.That) + b * off.T_hat;
   const int tile = blockIdx.x;
   const int qy = tile / d.tiles_x, qx0 = (tile - qy * d.tiles_x) * d.tqx;
   switch (d.C) {
@@ -148,7 +159,7 @@ __global__ __launch_bounds__(kThreads) void k_apply(const ImgDesc d, uint32_t s_
 }
 
 typedef void (*SearchKernel)(const ImgDesc, float);
-typedef void (*ApplyKernel)(const ImgDesc, uint32_t);
+typedef void (*ApplyKernel)(const ImgDesc, uint32_t, const ApplyBatch);
 
 template <int KW, int P, typename T>
 static SearchKernel pick_search_t(int mode, bool fused) {
@@ -279,6 +290,78 @@ static glu_status run_search(const glu_image* I, const glu_image* I_low, const g
   return GLU_OK;
 }
 
+// Validates a batch of n images of one size: n in 0..65535, strides >= 0,
+// and outputs of different images that do not overlap.
+glu_status check_batch(int32_t n, const glu_batch_strides* bs, bool backward) {
+  if (n < 0 || n > 65535) return fail(GLU_ERR_PARAM, "batch of %d images outside 0..65535", n);
+  if (n > 1 && !bs) return fail(GLU_ERR_NULL, "batch strides are NULL");
+  if (bs && (bs->theta < 0 || bs->T_low < 0 || bs->T_hat < 0 || bs->grad_T_low < 0 || bs->grad_alpha < 0))
+    return fail(GLU_ERR_PARAM, "negative batch stride");
+  (void)backward;
+  return GLU_OK;
+}
+
+static glu_status apply_batched(int32_t n, const glu_batch_strides* bs, const glu_theta* theta,
+                                const glu_image* T_low, const glu_params* p, glu_image* T_hat, void* stream) {
+  glu_status st;
+  if ((st = check_batch(n, bs, false))) return st;
+  if ((st = check_params(p))) return st;
+  if ((st = check_image(T_low, "T_low", 1, 4))) return st;
+  if ((st = check_image(T_hat, "T_hat", 1, 4))) return st;
+  const int H = T_hat->height, W = T_hat->width;
+  if ((st = check_theta(theta, H, W, true))) return st;
+  const int h = ceil_div(H, p->s), w = ceil_div(W, p->s);
+  if (T_low->height != h || T_low->width != w) return fail(GLU_ERR_SHAPE, "T_low must be ceil(H/s) x ceil(W/s)");
+  if (T_low->channels != T_hat->channels) return fail(GLU_ERR_SHAPE, "T_low and T_hat channel counts differ");
+  if (T_low->dtype != T_hat->dtype) return fail(GLU_ERR_DTYPE, "T_low and T_hat dtypes differ");
+  if (n > 1 && bs->T_hat < (int64_t)(H - 1) * T_hat->row_stride + (int64_t)W * T_hat->channels)
+    return fail(GLU_ERR_SHAPE, "T_hat batch stride makes images overlap");
+  if ((int64_t)H * W == 0 || n == 0) return GLU_OK;
+  ApplyBatch off{};
+  if (n > 1) {
+    off.theta = bs->theta;
+    off.T_low = bs->T_low;
+    off.T_hat = bs->T_hat;
+  }
+  ImgDesc d{};
+  d.T = T_low->data;
+  d.That = T_hat->data;
+  d.code = theta->code;
+  d.alpha = theta->alpha;
+  d.T_stride = T_low->row_stride;
+  d.That_stride = T_hat->row_stride;
+  d.th_stride = theta->row_stride;
+  d.H = H;
+  d.W = W;
+  d.h = h;
+  d.w = w;
+  d.s = p->s;
+  d.k = p->k;
+  d.C = T_low->channels;
+  d.dtype = T_low->dtype;
+  const int P = (p->s % 4 == 0) ? 4 : 1;
+  const int es = (int)dtype_size(T_low->dtype);
+  d.vec = launch_vec_flags(d, P, es);
+  if (aligned(T_hat->data, 16) && (T_hat->row_stride * es) % 16 == 0) d.vec |= VEC_TW;
+  // every image of the batch must keep the alignment of the first
+  if (off.theta % 4) d.vec &= ~VEC_THETA;
+  if ((off.T_hat * es) % 16) d.vec &= ~(VEC_TW | VEC_T);
+  d.tqx = apply_tile_width(p->s, P, p->k, d.C, es);
+  d.tqy = 1;
+  d.tiles_x = ceil_div(w, d.tqx);
+  d.tiles_y = h;
+  const int64_t groups = (int64_t)d.tiles_x * h;
+  if (groups > 0x7fffffff) return fail(GLU_ERR_UNSUPPORTED, "image too large");
+  const uint32_t s_magic = (uint32_t)std::min<uint64_t>(0xffffffffull, (1ull << 32) / (uint64_t)p->s);
+  const size_t lds = 16 * (size_t)apply_tile_words(d.tqx, p->k, P, d.C, es);
+  ApplyKernel kern = pick_apply(p->k, P, T_low->dtype);
+  hipLaunchKernelGGL(kern, dim3((unsigned)groups, (unsigned)n), dim3(kThreads), lds, (hipStream_t)stream, d, s_magic,
+                     off);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "apply launch");
+  return GLU_OK;
+}
+
 }  // namespace glu
 
 using namespace glu;
@@ -360,55 +443,6 @@ glu_status glu_search_apply(const glu_image* I, const glu_image* I_low, const gl
   return run_search(I, I_low, T_low, p, theta, err, T_hat, true, stream);
 }
 
-glu_status glu_apply(const glu_theta* theta, const glu_image* T_low, const glu_params* p, glu_image* T_hat,
-                     void* stream) {
-  clear_error();
-  glu_status st;
-  if ((st = check_params(p))) return st;
-  if ((st = check_image(T_low, "T_low", 1, 4))) return st;
-  if ((st = check_image(T_hat, "T_hat", 1, 4))) return st;
-  const int H = T_hat->height, W = T_hat->width;
-  if ((st = check_theta(theta, H, W, true))) return st;
-  const int h = ceil_div(H, p->s), w = ceil_div(W, p->s);
-  if (T_low->height != h || T_low->width != w) return fail(GLU_ERR_SHAPE, "T_low must be ceil(H/s) x ceil(W/s)");
-  if (T_low->channels != T_hat->channels) return fail(GLU_ERR_SHAPE, "T_low and T_hat channel counts differ");
-  if (T_low->dtype != T_hat->dtype) return fail(GLU_ERR_DTYPE, "T_low and T_hat dtypes differ");
-  if ((int64_t)H * W == 0) return GLU_OK;
-  ImgDesc d{};
-  d.T = T_low->data;
-  d.That = T_hat->data;
-  d.code = theta->code;
-  d.alpha = theta->alpha;
-  d.T_stride = T_low->row_stride;
-  d.That_stride = T_hat->row_stride;
-  d.th_stride = theta->row_stride;
-  d.H = H;
-  d.W = W;
-  d.h = h;
-  d.w = w;
-  d.s = p->s;
-  d.k = p->k;
-  d.C = T_low->channels;
-  d.dtype = T_low->dtype;
-  const int P = (p->s % 4 == 0) ? 4 : 1;
-  const int es = (int)dtype_size(T_low->dtype);
-  d.vec = launch_vec_flags(d, P, es);
-  if (aligned(T_hat->data, 16) && (T_hat->row_stride * es) % 16 == 0) d.vec |= VEC_TW;
-  d.tqx = apply_tile_width(p->s, P, p->k, d.C, es);
-  d.tqy = 1;
-  d.tiles_x = ceil_div(w, d.tqx);
-  d.tiles_y = h;
-  const int64_t groups = (int64_t)d.tiles_x * h;
-  if (groups > 0x7fffffff) return fail(GLU_ERR_UNSUPPORTED, "image too large");
-  const uint32_t s_magic = (uint32_t)std::min<uint64_t>(0xffffffffull, (1ull << 32) / (uint64_t)p->s);
-  const size_t lds = 16 * (size_t)apply_tile_words(d.tqx, p->k, P, d.C, es);
-  ApplyKernel kern = pick_apply(p->k, P, T_low->dtype);
-  hipLaunchKernelGGL(kern, dim3((unsigned)groups), dim3(kThreads), lds, (hipStream_t)stream, d, s_magic);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return hip_fail(e, "apply launch");
-  return GLU_OK;
-}
-
 glu_status glu_downsample(const glu_image* I, glu_image* I_low, int32_t s, glu_down_mode mode, void* stream) {
   clear_error();
   glu_status st;
@@ -453,6 +487,22 @@ glu_status glu_theta_expand(const glu_theta* theta, const glu_params* p, int64_t
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "theta_expand launch");
   return GLU_OK;
+}
+
+}  // extern "C"
+
+extern "C" {
+
+glu_status glu_apply(const glu_theta* theta, const glu_image* T_low, const glu_params* p, glu_image* T_hat,
+                     void* stream) {
+  clear_error();
+  return apply_batched(1, nullptr, theta, T_low, p, T_hat, stream);
+}
+
+glu_status glu_apply_batched(int32_t n, const glu_batch_strides* strides, const glu_theta* theta,
+                             const glu_image* T_low, const glu_params* p, glu_image* T_hat, void* stream) {
+  clear_error();
+  return apply_batched(n, strides, theta, T_low, p, T_hat, stream);
 }
 
 }  // extern "C"

@@ -47,7 +47,24 @@ struct BwdArgs {
   int32_t groups_x;     // workgroups per LR row
   uint32_t s_magic;     // floor(2^32 / s) for udiv_rt
   uint32_t vec;         // VEC_THETA | VEC_G | VEC_T(dalpha rows)
+  // element offsets between the images of a batch (blockIdx.y)
+  int64_t b_th, b_T, b_G, b_da, b_S, b_dT;
 };
+
+// The arguments of image blockIdx.y of a batch.
+template <typename T>
+__device__ __forceinline__ BwdArgs batch_image(const BwdArgs& a0) {
+  BwdArgs a = a0;
+  const int64_t b = blockIdx.y;
+  a.code += b * a0.b_th;
+  a.alpha += b * a0.b_th;
+  a.T = static_cast<const T*>(a0.T) + b * a0.b_T;
+  a.G += b * a0.b_G;
+  if (a.dalpha) a.dalpha += b * a0.b_da;
+  if (a.S) a.S += b * a0.b_S;
+  if (a.dT) a.dT += b * a0.b_dT;
+  return a;
+}
 
 // Loads C <= 4 gradient channels of pixels x .. x+P-1 (vector path for
 // P = 4, C = 3 or 1 on aligned rows).
@@ -278,8 +295,9 @@ __device__ __forceinline__ void bwd_block(const BwdArgs& a, float4* smem) {
 }
 
 template <typename T, int P, int KW, int C>
-__global__ __launch_bounds__(kThreads) void k_bwd_block(const BwdArgs a) {
+__global__ __launch_bounds__(kThreads) void k_bwd_block(const BwdArgs a0) {
   extern __shared__ float4 smem[];
+  const BwdArgs a = batch_image<T>(a0);
   bwd_block<T, P, KW, C>(a, smem);
 }
 
@@ -306,7 +324,8 @@ static BwdKernel pick_bwd(bool f16, int P, int k, int C) {
 }
 
 template <int KW, int C>
-__global__ __launch_bounds__(256) void k_bwd_lr(const BwdArgs a) {
+__global__ __launch_bounds__(256) void k_bwd_lr(const BwdArgs a0) {
+  const BwdArgs a = batch_image<float>(a0);  // T is not read here
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t hw = (int64_t)a.h * a.w;
   if (q >= hw) return;
@@ -363,11 +382,17 @@ size_t glu_apply_backward_workspace(int32_t H, int32_t W, int32_t C, const glu_p
   return (size_t)(h * w * p->k * p->k * C) * sizeof(float);
 }
 
-glu_status glu_apply_backward(const glu_theta* theta, const glu_image* T_low, const glu_params* p,
-                              const glu_image* grad_T_hat, glu_image* grad_T_low, float* grad_alpha, void* workspace,
-                              size_t ws_bytes, void* stream) {
-  clear_error();
+size_t glu_apply_backward_batched_workspace(int32_t n, int32_t H, int32_t W, int32_t C, const glu_params* p) {
+  if (n < 0) return 0;
+  return (size_t)n * glu_apply_backward_workspace(H, W, C, p);
+}
+
+static glu_status backward_batched(int32_t n, const glu_batch_strides* bs, const glu_theta* theta,
+                                   const glu_image* T_low, const glu_params* p, const glu_image* grad_T_hat,
+                                   glu_image* grad_T_low, float* grad_alpha, void* workspace, size_t ws_bytes,
+                                   void* stream) {
   glu_status st;
+  if ((st = check_batch(n, bs, true))) return st;
   if ((st = check_params(p))) return st;
   if ((st = check_image(T_low, "T_low", 1, 4))) return st;
   if ((st = check_image(grad_T_hat, "grad_T_hat", 1, 4, false))) return st;
@@ -382,13 +407,19 @@ glu_status glu_apply_backward(const glu_theta* theta, const glu_image* T_low, co
       return fail(GLU_ERR_SHAPE, "grad_T_low must match T_low");
   }
   if (grad_alpha && reinterpret_cast<uintptr_t>(grad_alpha) % 4) return fail(GLU_ERR_ALIGN, "grad_alpha not aligned");
-  if (grad_T_low && (int64_t)H * W > 0) {
-    const size_t need = glu_apply_backward_workspace(H, W, C, p);
+  if (n > 1) {
+    if (grad_T_low && bs->grad_T_low < (int64_t)(h - 1) * grad_T_low->row_stride + (int64_t)w * C)
+      return fail(GLU_ERR_SHAPE, "grad_T_low batch stride makes images overlap");
+    if (grad_alpha && bs->grad_alpha < (int64_t)(H - 1) * theta->row_stride + W)
+      return fail(GLU_ERR_SHAPE, "grad_alpha batch stride makes images overlap");
+  }
+  if (grad_T_low && (int64_t)H * W > 0 && n > 0) {
+    const size_t need = glu_apply_backward_batched_workspace(n, H, W, C, p);
     if (!workspace || ws_bytes < need)
       return fail(GLU_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
     if (reinterpret_cast<uintptr_t>(workspace) % 4) return fail(GLU_ERR_ALIGN, "workspace not aligned");
   }
-  if ((int64_t)H * W == 0) return GLU_OK;
+  if ((int64_t)H * W == 0 || n == 0) return GLU_OK;
   if (!grad_T_low && !grad_alpha) return GLU_OK;
   BwdArgs a{};
   a.code = theta->code;
@@ -409,18 +440,29 @@ glu_status glu_apply_backward(const glu_theta* theta, const glu_image* T_low, co
   a.s = p->s;
   a.k = p->k;
   a.C = C;
+  if (n > 1) {
+    a.b_th = bs->theta;
+    a.b_T = bs->T_low;
+    a.b_G = bs->T_hat;
+    a.b_da = bs->grad_alpha;
+    a.b_dT = bs->grad_T_low;
+    a.b_S = (int64_t)(glu_apply_backward_workspace(H, W, C, p) / sizeof(float));
+  }
   bwd_geometry(p->s, p->k, w, a.nb, a.rows_chunk);
   a.groups_x = ceil_div(w, a.nb);
   a.s_magic = (uint32_t)std::min<uint64_t>(0xffffffffull, (1ull << 32) / (uint64_t)p->s);
   const int P = (p->s % 4 == 0) ? 4 : 1;
   {
-    // alignment of the vector paths (all with x a multiple of 4)
-    auto al = [](const void* q, size_t n) { return (reinterpret_cast<uintptr_t>(q) % n) == 0; };
+    // alignment of the vector paths (all with x a multiple of 4), for every
+    // image of the batch
+    auto al = [](const void* q, size_t m) { return (reinterpret_cast<uintptr_t>(q) % m) == 0; };
     uint32_t v = 0;
     if (P == 4 && theta->row_stride % 4 == 0 && al(theta->code, 8) && al(theta->alpha, 16) &&
-        (!grad_alpha || al(grad_alpha, 16)))
+        (!grad_alpha || al(grad_alpha, 16)) && a.b_th % 4 == 0 && a.b_da % 4 == 0)
       v |= VEC_THETA | VEC_T;
-    if (P == 4 && (C == 3 || C == 1) && grad_T_hat->row_stride % 4 == 0 && al(grad_T_hat->data, 16)) v |= VEC_G;
+    if (P == 4 && (C == 3 || C == 1) && grad_T_hat->row_stride % 4 == 0 && al(grad_T_hat->data, 16) &&
+        a.b_G % 4 == 0)
+      v |= VEC_G;
     a.vec = v;
   }
   const size_t lds = (size_t)16 * bwd_lds_words(p->k, a.nb, p->s, a.rows_chunk);
@@ -428,17 +470,34 @@ glu_status glu_apply_backward(const glu_theta* theta, const glu_image* T_low, co
   if (groups > 0x7fffffff) return fail(GLU_ERR_UNSUPPORTED, "image too large");
   hipStream_t sm = (hipStream_t)stream;
   BwdKernel kern = pick_bwd(T_low->dtype == GLU_F16, P, p->k, C);
-  hipLaunchKernelGGL(kern, dim3((unsigned)groups), dim3(kThreads), lds, sm, a);
+  hipLaunchKernelGGL(kern, dim3((unsigned)groups, (unsigned)n), dim3(kThreads), lds, sm, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "backward pass 1 launch");
   if (grad_T_low) {
-    const int64_t n = (int64_t)h * w;
+    const int64_t cells = (int64_t)h * w;
     BwdKernel lr = p->k == 3 ? pick_lr_c<3>(C) : pick_lr_c<0>(C);
-    hipLaunchKernelGGL(lr, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, sm, a);
+    hipLaunchKernelGGL(lr, dim3((unsigned)((cells + 255) / 256), (unsigned)n), dim3(256), 0, sm, a);
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "backward pass 2 launch");
   }
   return GLU_OK;
+}
+
+glu_status glu_apply_backward(const glu_theta* theta, const glu_image* T_low, const glu_params* p,
+                              const glu_image* grad_T_hat, glu_image* grad_T_low, float* grad_alpha, void* workspace,
+                              size_t ws_bytes, void* stream) {
+  clear_error();
+  return backward_batched(1, nullptr, theta, T_low, p, grad_T_hat, grad_T_low, grad_alpha, workspace, ws_bytes,
+                          stream);
+}
+
+glu_status glu_apply_backward_batched(int32_t n, const glu_batch_strides* strides, const glu_theta* theta,
+                                      const glu_image* T_low, const glu_params* p, const glu_image* grad_T_hat,
+                                      glu_image* grad_T_low, float* grad_alpha, void* workspace, size_t ws_bytes,
+                                      void* stream) {
+  clear_error();
+  return backward_batched(n, strides, theta, T_low, p, grad_T_hat, grad_T_low, grad_alpha, workspace, ws_bytes,
+                          stream);
 }
 
 }  // extern "C"

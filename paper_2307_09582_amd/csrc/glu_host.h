@@ -52,6 +52,9 @@ int kernel_variant(int k, int P, int mode, int dtype);
 // VEC_* alignment flags of a launch (vector loads / stores allowed).
 uint32_t launch_vec_flags(const ImgDesc& d, int P, size_t esize);
 
+// Batch of n images of one size (glu_*_batched): n and stride checks.
+glu_status check_batch(int32_t n, const glu_batch_strides* bs, bool backward);
+
 // Apply tile width in LR columns (see apply_tile).
 int apply_tile_width(int s, int P, int k, int C, int esize);
 

@@ -118,8 +118,24 @@ def search(I, I_low, s, k=3, eps=EPS, mode="exhaustive", return_err=False, theta
     return (theta, err) if return_err else theta
 
 
+def _batch_view(t: torch.Tensor, name: str, dims: int):
+    """(first image, batch stride in elements) of a (B, ...) tensor."""
+    if t.dim() != dims + 1:
+        raise ValueError("%s must have a leading batch dimension" % name)
+    return t[0], (t.stride(0) if t.shape[0] > 1 else 0)
+
+
+def _theta_batch(th: Theta):
+    if th.code.dim() != 3 or th.alpha.shape != th.code.shape or th.code.stride() != th.alpha.stride():
+        raise ValueError("batched theta code and alpha must both be (B, H, W) with one layout")
+    return Theta(th.code[0], th.alpha[0]), (th.code.stride(0) if th.code.shape[0] > 1 else 0)
+
+
 def apply(theta: Theta, T_low: torch.Tensor, s: int, k: int = 3, out: torch.Tensor | None = None):
-    """Eq. 1 with a given Theta."""
+    """Eq. 1 with a given Theta.  T_low (h, w, C) with Theta (H, W), or a batch:
+    T_low (B, h, w, C) with Theta (B, H, W), in one launch."""
+    if T_low.dim() == 4:
+        return _apply_batched(theta, T_low, s, k, out)
     H, W = theta.shape
     if out is None:
         out = torch.empty((H, W, T_low.shape[2]), dtype=T_low.dtype, device=T_low.device)
@@ -128,6 +144,29 @@ def apply(theta: Theta, T_low: torch.Tensor, s: int, k: int = 3, out: torch.Tens
     L.check(
         lib.glu_apply(
             C.byref(_theta(theta)), C.byref(_img(T_low, "T_low")), C.byref(p), C.byref(_img(out, "T_hat")), _stream()
+        )
+    )
+    return out
+
+
+def _apply_batched(theta: Theta, T_low, s, k, out):
+    B = T_low.shape[0]
+    H, W = theta.code.shape[1:]
+    if theta.code.shape[0] != B:
+        raise ValueError("theta and T_low batch sizes differ")
+    if out is None:
+        out = torch.empty((B, H, W, T_low.shape[3]), dtype=T_low.dtype, device=T_low.device)
+    if B == 0:
+        return out
+    th0, sth = _theta_batch(theta)
+    T0, sT = _batch_view(T_low, "T_low", 3)
+    o0, so = _batch_view(out, "out", 3)
+    bs = L.glu_batch_strides(sth, sT, so, 0, 0)
+    p = _params(s, k, EPS)
+    L.check(
+        L.load().glu_apply_batched(
+            B, C.byref(bs), C.byref(_theta(th0)), C.byref(_img(T0, "T_low")), C.byref(p), C.byref(_img(o0, "T_hat")),
+            _stream(),
         )
     )
     return out
@@ -187,7 +226,13 @@ def apply_backward_workspace(H: int, W: int, channels: int, s: int, k: int = 3) 
 
 def apply_backward(theta: Theta, T_low, grad_T_hat, s, k=3, need_T_low=True, need_alpha=True, workspace=None,
                    out_T_low=None, out_alpha=None):
-    """Gradients of Eq. 1 (indices fixed): returns (grad_T_low or None, grad_alpha or None)."""
+    """Gradients of Eq. 1 (indices fixed): returns (grad_T_low or None, grad_alpha or None).
+
+    Batched when T_low is (B, h, w, C) (Theta (B, H, W), grad_T_hat
+    (B, H, W, C)): one launch per pass for the whole batch."""
+    if T_low.dim() == 4:
+        return _apply_backward_batched(theta, T_low, grad_T_hat, s, k, need_T_low, need_alpha, workspace, out_T_low,
+                                       out_alpha)
     H, W = theta.shape
     Cn = T_low.shape[2]
     gT = None
@@ -211,6 +256,63 @@ def apply_backward(theta: Theta, T_low, grad_T_hat, s, k=3, need_T_low=True, nee
             C.byref(p),
             C.byref(_img(grad_T_hat, "grad_T_hat")),
             C.byref(_img(gT, "grad_T_low")) if gT is not None else None,
+            C.c_void_p(ga.data_ptr() if ga is not None and ga.numel() else None),
+            C.c_void_p(workspace.data_ptr() if workspace is not None else None),
+            ws_bytes,
+            _stream(),
+        )
+    )
+    return gT, ga
+
+
+def apply_backward_batched_workspace(B: int, H: int, W: int, channels: int, s: int, k: int = 3) -> int:
+    lib = L.load()
+    p = _params(s, k, EPS)
+    return int(lib.glu_apply_backward_batched_workspace(int(B), int(H), int(W), int(channels), C.byref(p)))
+
+
+def _apply_backward_batched(theta, T_low, grad_T_hat, s, k, need_T_low, need_alpha, workspace, out_T_low, out_alpha):
+    B = T_low.shape[0]
+    H, W = theta.code.shape[1:]
+    Cn = T_low.shape[3]
+    if theta.code.shape[0] != B or grad_T_hat.shape[0] != B:
+        raise ValueError("theta, T_low and grad_T_hat batch sizes differ")
+    gT = None
+    if need_T_low:
+        gT = out_T_low if out_T_low is not None else torch.empty(T_low.shape, dtype=torch.float32,
+                                                                 device=T_low.device)
+    ga = None
+    if need_alpha:
+        ga = out_alpha if out_alpha is not None else torch.empty((B, H, W), dtype=torch.float32, device=T_low.device)
+    if B == 0:
+        return gT, ga
+    th0, sth = _theta_batch(theta)
+    T0, sT = _batch_view(T_low, "T_low", 3)
+    G0, sG = _batch_view(grad_T_hat, "grad_T_hat", 3)
+    sgT, sga = 0, 0
+    if gT is not None:
+        gT0, sgT = _batch_view(gT, "grad_T_low", 3)
+    if ga is not None:
+        if ga.dim() != 3 or ga.shape[1:] != (H, W) or (H > 1 and ga.stride(1) != th0.code.stride(0)):
+            raise ValueError("grad_alpha must be (B, H, W) with Theta's row stride")
+        sga = ga.stride(0) if B > 1 else 0
+    bs = L.glu_batch_strides(sth, sT, sG, sgT, sga)
+    p = _params(s, k, EPS)
+    lib = L.load()
+    ws_bytes = 0
+    if need_T_low:
+        ws_bytes = int(lib.glu_apply_backward_batched_workspace(B, H, W, Cn, C.byref(p)))
+        if workspace is None or workspace.numel() * workspace.element_size() < ws_bytes:
+            workspace = torch.empty(max(1, ws_bytes // 4), dtype=torch.float32, device=T_low.device)
+    L.check(
+        lib.glu_apply_backward_batched(
+            B,
+            C.byref(bs),
+            C.byref(_theta(th0)),
+            C.byref(_img(T0, "T_low")),
+            C.byref(p),
+            C.byref(_img(G0, "grad_T_hat")),
+            C.byref(_img(gT0, "grad_T_low")) if gT is not None else None,
             C.c_void_p(ga.data_ptr() if ga is not None and ga.numel() else None),
             C.c_void_p(workspace.data_ptr() if workspace is not None else None),
             ws_bytes,
@@ -376,7 +478,9 @@ class GluApply(torch.autograd.Function):
     """Eq. 1 as an autograd function of (alpha, T_low); the codes are constant.
 
     forward(alpha, T_low, code, s, k) -> T_hat.  The backward is the
-    hand-written deterministic gather of glu_apply_backward.
+    hand-written deterministic gather of glu_apply_backward.  With a batch
+    dimension (alpha and code (B, H, W), T_low (B, h, w, C)) forward and
+    backward each run the whole batch in one launch per pass.
     """
 
     @staticmethod

@@ -119,3 +119,33 @@ def test_empty_images_return_ok_without_launch():
     # zero pixels: valid arguments, nothing to do, no HIP call is made
     st = _search(_img(ptr=0, H=0, W=5), _img(ptr=0, H=0, W=2), _params(), _theta(H=0, W=5, code=0, alpha=0))
     assert st == 0
+
+
+def test_batched_validation():
+    lib = L.load()
+    th = _theta()
+    p = _params()
+    Tl = _img(H=2, W=2, Cn=1)
+    Th = _img(Cn=1)
+    bs = L.glu_batch_strides(64, 4, 64, 0, 0)
+    # batch size outside 0..65535, NULL strides for n > 1, negative stride
+    assert lib.glu_apply_batched(-1, C.byref(bs), C.byref(th), C.byref(Tl), C.byref(p), C.byref(Th), None) == 4
+    assert lib.glu_apply_batched(70000, C.byref(bs), C.byref(th), C.byref(Tl), C.byref(p), C.byref(Th), None) == 4
+    assert lib.glu_apply_batched(2, None, C.byref(th), C.byref(Tl), C.byref(p), C.byref(Th), None) == 1
+    neg = L.glu_batch_strides(64, -4, 64, 0, 0)
+    assert lib.glu_apply_batched(2, C.byref(neg), C.byref(th), C.byref(Tl), C.byref(p), C.byref(Th), None) == 4
+    # output images that overlap
+    small = L.glu_batch_strides(64, 4, 8, 0, 0)
+    assert lib.glu_apply_batched(2, C.byref(small), C.byref(th), C.byref(Tl), C.byref(p), C.byref(Th), None) == 2
+    # an empty batch is valid and launches nothing
+    assert lib.glu_apply_batched(0, None, C.byref(th), C.byref(Tl), C.byref(p), C.byref(Th), None) == 0
+    G = _img(Cn=1)
+    gT = _img(ptr=0x5000, H=2, W=2, Cn=1)
+    ws = lib.glu_apply_backward_batched_workspace(3, 8, 8, 1, C.byref(p))
+    assert ws == 3 * lib.glu_apply_backward_workspace(8, 8, 1, C.byref(p))
+    bsb = L.glu_batch_strides(64, 4, 64, 1, 64)
+    assert lib.glu_apply_backward_batched(3, C.byref(bsb), C.byref(th), C.byref(Tl), C.byref(p), C.byref(G),
+                                          C.byref(gT), None, 0x6000, ws, None) == 2  # grad_T_low overlap
+    bsb = L.glu_batch_strides(64, 4, 64, 4, 64)
+    assert lib.glu_apply_backward_batched(3, C.byref(bsb), C.byref(th), C.byref(Tl), C.byref(p), C.byref(G),
+                                          C.byref(gT), None, 0x6000, ws - 4, None) == 9  # workspace too small

@@ -171,3 +171,57 @@ def test_autograd_function_matches_torch_reference():
     lr.backward()
     np.testing.assert_allclose(host(al_t.grad).ravel(), ar.grad.numpy(), rtol=1e-4, atol=1e-9)
     np.testing.assert_allclose(host(T_t.grad).reshape(-1, 3), Tr.grad.numpy(), rtol=1e-4, atol=1e-9)
+
+
+@pytest.mark.parametrize("H,W,s,k,C,step", [(96, 136, 8, 3, 3, 1), (50, 70, 4, 5, 2, 2), (33, 29, 3, 3, 1, 1)])
+def test_batched_apply_and_backward_equal_per_image(H, W, s, k, C, step):
+    """glu_apply_batched / glu_apply_backward_batched give bitwise the results
+    of per-image calls, also for a strided view of a larger batch."""
+    glu = _glu()
+    log_case(test="batched_apply_backward", H=H, W=W, s=s, k=k, C=C, step=step)
+    B = 3
+    h, w = -(-H // s), -(-W // s)
+    rng = np.random.default_rng(H + W + s)
+    codes, alphas = [], []
+    for b in range(B * step):
+        code, alpha, _, _ = random_theta(H, W, s, k, seed=100 + b)
+        codes.append(code.view(np.int16))
+        alphas.append(alpha)
+    code = dev(np.stack(codes))[::step]
+    alpha = dev(np.stack(alphas))[::step]
+    T = dev(rng.uniform(0, 1, (B * step, h, w, C)).astype(np.float32))[::step]
+    G = dev(rng.normal(0, 1, (B * step, H, W, C)).astype(np.float32))[::step]
+    th = glu.Theta(code, alpha)
+    out = glu.apply(th, T, s, k)
+    gT, ga = glu.apply_backward(th, T, G, s, k)
+    for b in range(B):
+        thb = glu.Theta(code[b].contiguous(), alpha[b].contiguous())
+        ob = glu.apply(thb, T[b].contiguous(), s, k)
+        gTb, gab = glu.apply_backward(thb, T[b].contiguous(), G[b].contiguous(), s, k)
+        assert torch.equal(out[b], ob)
+        assert torch.equal(gT[b], gTb) and torch.equal(ga[b], gab)
+
+
+def test_batched_autograd_matches_loop():
+    """GluApply over a (B, H, W) batch: one forward and one backward launch per
+    pass, gradients equal to the per-image autograd calls."""
+    glu = _glu()
+    log_case(test="batched_autograd")
+    B, H, W, s, k, C = 4, 64, 80, 8, 3, 3
+    h, w = H // s, W // s
+    codes = [random_theta(H, W, s, k, seed=200 + b)[0].view(np.int16) for b in range(B)]
+    code = dev(np.stack(codes))
+    rng = np.random.default_rng(7)
+    alpha = dev(rng.uniform(0, 1, (B, H, W)).astype(np.float32)).requires_grad_(True)
+    T = dev(rng.uniform(0, 1, (B, h, w, C)).astype(np.float32)).requires_grad_(True)
+    target = dev(rng.uniform(0, 1, (B, H, W, C)).astype(np.float32))
+    loss = ((glu.glu_apply_autograd(alpha, T, code, s, k) - target) ** 2).mean()
+    loss.backward()
+    ga, gT = alpha.grad.clone(), T.grad.clone()
+    for b in range(B):
+        a1 = alpha.detach()[b].clone().requires_grad_(True)
+        T1 = T.detach()[b].clone().requires_grad_(True)
+        l1 = ((glu.glu_apply_autograd(a1, T1, code[b], s, k) - target[b]) ** 2).sum() / target.numel()
+        l1.backward()
+        assert torch.allclose(a1.grad, ga[b], rtol=1e-6, atol=1e-12)
+        assert torch.allclose(T1.grad, gT[b], rtol=1e-6, atol=1e-12)
