@@ -73,6 +73,10 @@ __all__ = [
     "eval_pairs_exhaustive",
     "eval_pairs_fast",
     "search_fast_given_anchor",
+    "self_upsampling_gradient",
+    "snap_to_block",
+    "joint_downsample_gradient",
+    "GradientJointResult",
 ]
 
 # Parameters fixed by the paper: eps of Eq. 4 (Sec. 3.1); window S = 3,
@@ -501,6 +505,98 @@ def joint_downsample(
         res.n_accepted.append(acc_count)
     res.err_sum_final = float(E.sum())
     return res
+
+
+# --------------------------------------------------------------------------
+# Gradient-driven joint downsampling (not in the paper)
+# --------------------------------------------------------------------------
+# An alternative to the trial replacements of Alg. 2, defined here rather
+# than taken from the paper: the LR guide moves along the gradient of the
+# self-upsampling error (Sec. 3.3 upsamples I_down itself and measures
+# ||I_hat - I||) through Eq. 1 with Theta held fixed, and every LR pixel is
+# then put back on a copy of one HR pixel of its own block, which keeps the
+# one-pixel-per-LR-pixel property of Sec. 3.3.
+def self_upsampling_gradient(I, L, a, b, alpha):
+    """D = d/dL of sum_p ||I_hat_p - I_p||^2 with I_hat = Eq. 1 applied to L
+    (Theta = (a, b, alpha) held fixed): G = 2 (I_hat - I), then the
+    gradient of Eq. 1 with respect to its LR target.  Returns (D (h, w, 3),
+    I_hat (H, W, 3))."""
+    I = np.asarray(I, dtype=np.float64)
+    L = np.asarray(L, dtype=np.float64)
+    H, W = I.shape[:2]
+    I_hat = apply(a, b, alpha, L).reshape(H, W, -1)
+    G = 2.0 * (I_hat - I)
+    _, dL = apply_backward(a, b, alpha, L, G)
+    return dL.reshape(L.shape), I_hat
+
+
+def snap_to_block(I, Z, s, decide=None):
+    """For every LR cell q, the HR pixel of its block {p : p_down = q} whose
+    colour is nearest to Z_q (squared Euclidean distance; ties to the
+    smallest HR linear index).  Returns the flat HR indices (h * w,)."""
+    I = np.asarray(I, dtype=np.float64)
+    Z = np.asarray(Z, dtype=np.float64)
+    H, W = I.shape[:2]
+    h, w = Z.shape[:2]
+    If = I.reshape(H * W, -1)
+    out = np.empty(h * w, dtype=np.int64)
+    for qy in range(h):
+        ys = np.arange(qy * s, min(H, qy * s + s))
+        for qx in range(w):
+            xs = np.arange(qx * s, min(W, qx * s + s))
+            members = (ys[:, None] * W + xs[None, :]).ravel()  # ascending HR index
+            dist = ((If[members] - Z[qy, qx]) ** 2).sum(axis=1)
+            p = int(members[int(np.argmin(dist))])  # first minimum
+            if decide is not None:
+                p = decide("snap", (qy * w + qx, members, dist), p)
+            out[qy * w + qx] = p
+    return out
+
+
+@dataclass
+class GradientJointResult:
+    L: np.ndarray
+    a: np.ndarray
+    b: np.ndarray
+    alpha: np.ndarray
+    err: np.ndarray
+    err_sums: list = field(default_factory=list)  # sum of E after 0, 1, ... steps
+    best_step: int = 0
+
+
+def joint_downsample_gradient(I, L0, s, k=WINDOW, eps=EPS, mode="exhaustive", eta=0.01, n_steps=3,
+                              keep_best=True, decide=None) -> GradientJointResult:
+    """Alternate the pair search with projected gradient steps on I_down.
+
+    From L = L0 and (Theta, E) = search(I, L), each step computes
+    D = self_upsampling_gradient(I, L, Theta), moves Z = L - eta D, sets
+    every L_q to the HR pixel of its block nearest to Z_q (snap_to_block)
+    and searches again.  Returns the L with the smallest sum of E seen (the
+    first such on equality) when keep_best, else the last one, with its
+    Theta and E and the sum of E after every step."""
+    I = np.asarray(I, dtype=np.float64)
+    H, W = I.shape[:2]
+    L = np.array(L0, dtype=np.float64, copy=True)
+    h, w = L.shape[:2]
+    If = I.reshape(H * W, -1)
+    r = search(I, L, s, k, eps, mode)
+    best = (float(r.err.sum()), L.copy(), r, 0)
+    sums = [best[0]]
+    for t in range(1, n_steps + 1):
+        D, _ = self_upsampling_gradient(I, L, r.a, r.b, r.alpha)
+        Z = L - eta * D
+        pick = snap_to_block(I, Z, s, decide)
+        L = If[pick].reshape(h, w, -1).copy()
+        r = search(I, L, s, k, eps, mode)
+        e = float(r.err.sum())
+        sums.append(e)
+        if e < best[0]:
+            best = (e, L.copy(), r, t)
+    if keep_best:
+        e, L, r, t_best = best
+    else:
+        t_best = n_steps
+    return GradientJointResult(L=L, a=r.a, b=r.b, alpha=r.alpha, err=r.err, err_sums=sums, best_step=t_best)
 
 
 # --------------------------------------------------------------------------

@@ -49,6 +49,12 @@ MUTATIONS = [
      "            for dy, dx in ((-1, 0), (1, 0), (0, -1), (0, 1)):\n                if True:\n                    ny, nx"),
     ("regular grid samples the block corner", "ys = np.minimum(np.arange(h) * s + s // 2, H - 1)",
      "ys = np.minimum(np.arange(h) * s, H - 1)"),
+    ("gradient step uphill", "        Z = L - eta * D\n", "        Z = L + eta * D\n"),
+    ("loss gradient without its factor 2", "    G = 2.0 * (I_hat - I)\n", "    G = (I_hat - I)\n"),
+    ("snap keeps the last nearest pixel", "            p = int(members[int(np.argmin(dist))])  # first minimum",
+     "            p = int(members[len(dist) - 1 - int(np.argmin(dist[::-1]))])"),
+    ("snap block one column short", "            xs = np.arange(qx * s, min(W, qx * s + s))\n",
+     "            xs = np.arange(qx * s, min(W, qx * s + s - 1))\n"),
     ("affected set limited to the component's cells",
      "cells[max(0, qy - r) : qy + r + 1, max(0, qx - r) : qx + r + 1] = True",
      "cells[qy, qx] = True"),
@@ -76,6 +82,10 @@ def _pins():
         lambda: P.test_joint_constructed_rollback(),
         lambda: P.test_exact_ties_go_to_the_earliest_candidate(),
         lambda: P.test_joint_replacement_takes_the_largest_error(),
+        lambda: P.test_self_upsampling_gradient_finite_differences(),
+        lambda: P.test_snap_to_block_bruteforce(),
+        lambda: P.test_gradient_joint_fixed_points(),
+        lambda: P.test_gradient_joint_best_and_copies(),
     ]
 
 

@@ -559,3 +559,101 @@ def test_joint_replacement_takes_the_largest_error():
     d = res.log[0]
     assert d.q_pstar == [(2 * 8 + 2, 18 * 64 + 19)]
     assert np.array_equal(res.L[2, 2], np.array(far))
+
+
+# --------------------------------------------------------------------------
+# Gradient-driven joint downsampling (defined by the project, not the paper)
+# --------------------------------------------------------------------------
+def test_self_upsampling_gradient_finite_differences():
+    """D equals central finite differences of sum_p ||apply(Theta, L) - I||^2
+    with Theta fixed (the loss is quadratic in L, so central differences are
+    exact up to rounding)."""
+    s = 4
+    I = synth.voronoi(12, 16, n_cells=5, n_dots=1, dot_px=(1, 2), seed=11).astype(np.float64)
+    L = O.downsample_point(I, s) + 0.05 * np.random.default_rng(2).standard_normal((3, 4, 3))
+    r = O.search_exhaustive(I, L, s)
+    D, I_hat = O.self_upsampling_gradient(I, L, r.a, r.b, r.alpha)
+
+    def loss(Lx):
+        return float(((O.apply(r.a, r.b, r.alpha, Lx).reshape(I.shape) - I) ** 2).sum())
+
+    h = 1e-6
+    fd = np.zeros_like(L)
+    for idx in np.ndindex(L.shape):
+        Lp, Lm = L.copy(), L.copy()
+        Lp[idx] += h
+        Lm[idx] -= h
+        fd[idx] = (loss(Lp) - loss(Lm)) / (2 * h)
+    np.testing.assert_allclose(D, fd, rtol=1e-6, atol=1e-7)
+    np.testing.assert_allclose(I_hat.reshape(-1, 3), O.apply(r.a, r.b, r.alpha, L), atol=0)
+
+
+def test_snap_to_block_bruteforce():
+    """The nearest pixel of each block, by an independent double loop over all
+    HR pixels (first minimum in raster order), including ragged border blocks
+    and exact ties."""
+    rng = np.random.default_rng(5)
+    H, W, s = 11, 13, 4
+    I = rng.integers(0, 4, (H, W, 3)) / 4.0  # coarse colours: many exact ties
+    Z = rng.uniform(0, 1, (3, 4, 3))
+    # in every other block, Z is the colour of a pixel that recurs later in the block
+    for qy in range(3):
+        for qx in range(0, 4, 2):
+            y0, x0 = qy * s, qx * s
+            y1, x1 = min(H, y0 + s) - 1, min(W, x0 + s) - 1
+            I[y1, x1] = I[y0, x0 + 1]
+            Z[qy, qx] = I[y0, x0 + 1]
+    # and in block (0, 1) the nearest pixel is the only one of its colour, in
+    # the block's last column
+    I[1, 2 * s - 1] = (0.9, 0.9, 0.9)
+    Z[0, 1] = (0.88, 0.9, 0.91)
+    got = O.snap_to_block(I, Z, s)
+    for qy in range(3):
+        for qx in range(4):
+            best, arg = None, None
+            for y in range(H):
+                for x in range(W):
+                    if y // s != qy or x // s != qx:
+                        continue
+                    d = sum((float(I[y, x, c]) - float(Z[qy, qx, c])) ** 2 for c in range(3))
+                    if best is None or d < best:
+                        best, arg = d, y * W + x
+            assert got[qy * 4 + qx] == arg
+
+
+def test_gradient_joint_fixed_points():
+    """eta = 0 keeps a regular-grid I_down (each L_q is a pixel of its block, at
+    distance 0); a nearest-neighbour copy image has E = 0 and zero gradient."""
+    s = 4
+    I = synth.voronoi(24, 32, n_cells=6, n_dots=2, dot_px=(1, 2), seed=3).astype(np.float64)
+    L0 = O.downsample_point(I, s)
+    r = O.joint_downsample_gradient(I, L0, s, eta=0.0, n_steps=2, keep_best=False)
+    np.testing.assert_array_equal(r.L, L0)
+    assert r.err_sums[0] == r.err_sums[1] == r.err_sums[2]
+    Lc = np.random.default_rng(4).uniform(0, 1, (6, 8, 3))
+    Inn = np.repeat(np.repeat(Lc, s, axis=0), s, axis=1)
+    r = O.joint_downsample_gradient(Inn, Lc, s, eta=0.05, n_steps=2, keep_best=False)
+    np.testing.assert_array_equal(r.L, Lc)
+    assert max(r.err_sums) == 0.0
+
+
+def test_gradient_joint_best_and_copies():
+    """The returned I_down has the least sum of E seen (the first on ties), its
+    Theta and E are the search on it, and every LR pixel is a copy of an HR
+    pixel of its own block; on this image one step lowers the sum of E."""
+    s = 8
+    I = synth.voronoi(96, 120, n_cells=20, n_dots=10, dot_px=(1, 3), seed=7)
+    L0 = O.downsample_point(I, s)
+    r = O.joint_downsample_gradient(I, L0, s, eta=0.01, n_steps=3, keep_best=True)
+    assert r.err_sums[1] < r.err_sums[0]
+    assert float(r.err.sum()) == min(r.err_sums) == r.err_sums[r.best_step]
+    assert r.best_step == int(np.argmin(r.err_sums))
+    again = O.search_exhaustive(I, r.L, s)
+    np.testing.assert_array_equal(again.a, r.a)
+    np.testing.assert_array_equal(again.err, r.err)
+    h, w = L0.shape[:2]
+    If = I.astype(np.float64)
+    for qy in range(h):
+        for qx in range(w):
+            blk = If[qy * s : qy * s + s, qx * s : qx * s + s].reshape(-1, 3)
+            assert np.any(np.all(blk == r.L[qy, qx], axis=1))
