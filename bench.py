@@ -14,7 +14,8 @@ Prints ONE JSON line.  Beside the headline it carries, measured live with
 HIP events on the stream the kernels run on: per-kernel times of both search
 modes (search, apply, fused, and the two-kernel step), the roofline of the
 dominant kernel, the backward pass, and one entry per further workload:
-plain 512 x 512 x4, joint downsampling 2048 x 2048 x8 (5 rounds), 60 x 4K
+plain 512 x 512 x4, joint downsampling 2048 x 2048 x8 (5 rounds of
+Algorithm 2, and 5 steps of the gradient-driven form), 60 x 4K
 float16 video frames in one graph-captured persistent launch, an uneven
 batch of 64 images with autotuned tiles, and the backward over 16 x 1024^2.
 """
@@ -399,6 +400,17 @@ def _configs(np, torch, synth, glu, dev, stream, scene):
             "err_sum_initial": round(stats["err_sum_initial"], 3),
             "err_sum_final": round(stats["err_sum_final"], 3),
         }
+    # gradient-driven form of the joint downsampling on the same image and
+    # I_low0, 5 steps, eta 0.01, the best I_low kept
+    walls = []
+    for rep in range(3):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        Lg, thg, eg, sums, best = glu.joint_downsample_grad(I, L0, 8, 3, EPS, "exhaustive", eta=0.01, n_steps=5)
+        torch.cuda.synchronize()
+        walls.append(time.perf_counter() - t)
+    r["gradient_exhaustive"] = {"wall_ms": round(1e3 * sorted(walls)[1], 3), "eta": 0.01, "steps": 5,
+                                "err_sums": [round(v, 3) for v in sums], "best_step": best}
     out["joint_2048_x8_5rounds"] = r
     print("joint done", file=sys.stderr, flush=True)
     del I, L0

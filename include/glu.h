@@ -281,6 +281,42 @@ glu_status glu_joint_downsample(const glu_image* I, glu_image* I_low, const glu_
                                 glu_jd_log* log, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * glu_joint_downsample_grad - gradient-driven joint downsampling.  Defined
+ * by this library (not in the paper) as an alternative to the trial
+ * replacements of Algorithm 2; it keeps Sec. 3.3's rule that every LR guide
+ * pixel is a copy of one HR pixel of its own block.  From Theta, E =
+ * search(I, I_low), each of n_steps steps:
+ *   D   = d/dI_low of sum_p ||I_hat_p - I_p||^2, I_hat = Eq. 1 applied to
+ *         I_low itself, Theta held fixed (G = 2 (I_hat - I) through the
+ *         gradient of Eq. 1, as in glu_apply_backward);
+ *   I_low[q] = I[p*], p* the pixel of q's s x s block nearest (squared RGB
+ *         distance) to I_low[q] - eta D[q], ties to the smallest HR index;
+ *   Theta, E = search(I, I_low).
+ *
+ *   I          H x W x 3, GLU_F32.
+ *   I_low      in: initial guide, out: the result, ceil(H/s) x ceil(W/s) x 3,
+ *              GLU_F32.
+ *   eta        step size, finite, >= 0.
+ *   n_steps    0..64.
+ *   keep_best  non-zero: return the I_low of least sum of E seen (the first
+ *              on equality), with its Theta and E; zero: the last one.
+ *   theta      output, H x W (required).
+ *   err        nullable output, E with theta's row stride; when NULL, theta
+ *              must be dense (row_stride == W).
+ *   workspace  device, glu_joint_downsample_grad_workspace() bytes, 256-byte
+ *              aligned, caller-owned.
+ *   err_sums   nullable HOST array of n_steps + 1 doubles: sum of E after 0,
+ *              1, ... steps (fixed summation order).
+ *   best_step  nullable HOST int: the step whose I_low is returned.
+ * Synchronises the stream once per step.
+ * ------------------------------------------------------------------------- */
+size_t glu_joint_downsample_grad_workspace(int32_t H, int32_t W, const glu_params* p);
+glu_status glu_joint_downsample_grad(const glu_image* I, glu_image* I_low, const glu_params* p, float eta,
+                                     int32_t n_steps, int32_t keep_best, glu_theta* theta, float* err,
+                                     void* workspace, size_t ws_bytes, double* err_sums /* HOST */,
+                                     int32_t* best_step /* HOST */, void* stream);
+
+/* ---------------------------------------------------------------------------
  * Batched persistent execution: search + apply of many images or frames of
  * any mix of sizes, ratios s, windows k and storage types.  The items are
  * grouped by kernel variant (window 3, 5 or other; 4 or 1 pixels per strip,

@@ -22,6 +22,7 @@ from .glu import (  # noqa: F401
     empty_theta,
     glu_apply_autograd,
     joint_downsample,
+    joint_downsample_grad,
     joint_downsample_workspace,
     lr_shape,
     search,

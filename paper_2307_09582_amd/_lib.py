@@ -170,6 +170,12 @@ _SIGS = {
             C.c_void_p,
         ],
     ),
+    "glu_joint_downsample_grad_workspace": (C.c_size_t, [C.c_int32, C.c_int32, P(glu_params)]),
+    "glu_joint_downsample_grad": (
+        C.c_int,
+        [P(glu_image), P(glu_image), P(glu_params), C.c_float, C.c_int32, C.c_int32, P(glu_theta), C.c_void_p,
+         C.c_void_p, C.c_size_t, P(C.c_double), P(C.c_int32), C.c_void_p],
+    ),
     "glu_batch_plan_create": (C.c_int, [P(glu_batch_item), C.c_int32, P(glu_params), P(C.c_void_p)]),
     "glu_batch_plan_launch": (C.c_int, [C.c_void_p, C.c_void_p]),
     "glu_batch_plan_destroy": (None, [C.c_void_p]),

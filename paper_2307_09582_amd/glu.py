@@ -395,6 +395,32 @@ def joint_downsample(I, I_low0, s, k=3, eps=EPS, mode="exhaustive", tau=TAU, max
     return I_low, theta, err, stats, log
 
 
+def joint_downsample_grad(I, I_low0, s, k=3, eps=EPS, mode="exhaustive", eta=0.01, n_steps=3, keep_best=True,
+                          workspace=None):
+    """Gradient-driven joint downsampling (glu_joint_downsample_grad).
+
+    Returns (I_low, Theta, E, err_sums, best_step); I_low0 is not modified."""
+    H, W = I.shape[:2]
+    I_low = I_low0.clone()
+    theta = empty_theta(H, W, I.device)
+    err = torch.empty((H, W), dtype=torch.float32, device=I.device)
+    p = _params(s, k, eps, mode)
+    lib = L.load()
+    ws_bytes = int(lib.glu_joint_downsample_grad_workspace(H, W, C.byref(p)))
+    if workspace is None or workspace.numel() * workspace.element_size() < ws_bytes:
+        workspace = torch.empty(max(256, ws_bytes), dtype=torch.uint8, device=I.device)
+    sums = (C.c_double * (int(n_steps) + 1))()
+    best = C.c_int32(0)
+    L.check(
+        lib.glu_joint_downsample_grad(
+            C.byref(_img(I, "I")), C.byref(_img(I_low, "I_low")), C.byref(p), float(eta), int(n_steps),
+            1 if keep_best else 0, C.byref(_theta(theta)), C.c_void_p(err.data_ptr() if err.numel() else None),
+            C.c_void_p(workspace.data_ptr()), ws_bytes, sums, C.byref(best), _stream(),
+        )
+    )
+    return I_low, theta, err, list(sums), int(best.value)
+
+
 def _batch_item(it) -> L.glu_batch_item:
     th = it.get("theta")
     if th is not None:

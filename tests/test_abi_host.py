@@ -149,3 +149,30 @@ def test_batched_validation():
     bsb = L.glu_batch_strides(64, 4, 64, 4, 64)
     assert lib.glu_apply_backward_batched(3, C.byref(bsb), C.byref(th), C.byref(Tl), C.byref(p), C.byref(G),
                                           C.byref(gT), None, 0x6000, ws - 4, None) == 9  # workspace too small
+
+
+def test_joint_downsample_grad_validation():
+    lib = L.load()
+    p = _params(s=4)
+    I = _img(H=8, W=8)
+    Il = _img(ptr=0x4000, H=2, W=2)
+    th = _theta()
+    ws = lib.glu_joint_downsample_grad_workspace(8, 8, C.byref(p))
+    assert ws > 0
+
+    def call(I=I, Il=Il, eta=0.01, n=2, wsp=0x100000, wsb=ws, err=0x7000):
+        return lib.glu_joint_downsample_grad(C.byref(I), C.byref(Il), C.byref(p), eta, n, 1, C.byref(th), err, wsp,
+                                             wsb, None, None, None)
+
+    assert call(eta=-1.0) == 4
+    assert call(eta=float("inf")) == 4
+    assert call(n=65) == 4
+    assert call(I=_img(H=8, W=8, dt=L.GLU_F16)) == 3
+    assert call(Il=_img(ptr=0x4000, H=3, W=2)) == 2
+    assert call(wsb=ws - 1) == 9
+    assert call(wsp=0x100010) == 5
+    # a non-dense theta needs a caller E buffer
+    th2 = L.glu_theta(0x2000, 0x3000, 8, 8, 12)
+    st = lib.glu_joint_downsample_grad(C.byref(I), C.byref(Il), C.byref(p), 0.01, 2, 1, C.byref(th2), None,
+                                       0x100000, ws, None, None, None)
+    assert st == 2
