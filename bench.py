@@ -450,6 +450,35 @@ def _configs(np, torch, synth, glu, dev, stream, scene):
     torch.cuda.synchronize()
     print("video done", file=sys.stderr, flush=True)
 
+    # window and ratio sweep on the 4K frame (fused, Theta written), before
+    # any autotuning so that every shape runs its default tile:
+    # k in {3, 5, 7, 9} at s = 8, and s in {4, ..., 128} at k = 3
+    I = torch.from_numpy(scene.frame(0, sigma=0.01, dtype=np.float32)).to(dev)
+    thw = glu.empty_theta(H, W, dev)
+    ow = torch.empty_like(I)
+    sweep = {"k_at_s8": {}, "s_at_k3": {}}
+    Il8 = glu.downsample(I, 8, "point")
+    T8 = _lr_f1_torch(torch, Il8).contiguous()
+    for kk in (3, 5, 7, 9):
+        row = {}
+        for mode in ("exhaustive", "fast"):
+            n = 20 if kk <= 5 else 3
+            ms = _events_ms(torch, stream,
+                            lambda i: glu.search_apply(I, Il8, T8, 8, kk, EPS, mode, theta=thw, out=ow), n, 3)
+            row[mode] = {"us": round(1e3 * ms, 1), "Mpx_s": round(H * W / (ms * 1e-3) / 1e6, 1)}
+        sweep["k_at_s8"][str(kk)] = row
+    for ss in (4, 8, 16, 32, 64, 128):
+        Ils = glu.downsample(I, ss, "point")
+        Ts = _lr_f1_torch(torch, Ils).contiguous()
+        row = {}
+        for mode in ("exhaustive", "fast"):
+            ms = _events_ms(torch, stream,
+                            lambda i: glu.search_apply(I, Ils, Ts, ss, 3, EPS, mode, theta=thw, out=ow), 20, 5)
+            row[mode] = {"us": round(1e3 * ms, 1), "Mpx_s": round(H * W / (ms * 1e-3) / 1e6, 1)}
+        sweep["s_at_k3"][str(ss)] = row
+    out["sweep_4k"] = sweep
+    print("sweep done", file=sys.stderr, flush=True)
+
     # uneven batch: 64 images, sizes 720x480 .. 6000x4000, s in {4, 8, 16},
     # k in {3, 5}; crops of one seeded canvas with the same cell density
     specs = synth.uneven_batch_specs(64, seed=4)

@@ -92,7 +92,10 @@ TileChoice choose_tile(int s, int k, int mode, bool fused, bool table, int varia
   tc.P = (s % 4 == 0) ? 4 : 1;
   const int cols = kVariantCols[variant];
   tc.tqx = std::max(1, cols / s);
-  const int strips_target = kThreads * kVariantStripsPerThread[variant];
+  // the fast search keeps less per-strip state: its default tile gives each
+  // thread two strips, so the next strip's pixels load during the search
+  const int spt = (variant == 0 && mode == MODE_FAST) ? 2 : kVariantStripsPerThread[variant];
+  const int strips_target = kThreads * spt;
   const int rows = std::max(1, strips_target * tc.P / (tc.tqx * s));
   tc.tqy = std::max(1, rows / s);
   auto bytes = [&](const TileChoice& t) {

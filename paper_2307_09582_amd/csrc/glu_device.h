@@ -185,7 +185,9 @@ __device__ __forceinline__ PairK pair_consts(float4 Li, float4 Lj, float eps) {
   const float ex = Li.x - Lj.x, ey = Li.y - Lj.y, ez = Li.z - Lj.z;
   const float n = fmaf(ez, ez, fmaf(ey, ey, ex * ex));
   const float den = n + eps;
-  const float inv = den > 0.0f ? 1.0f / den : 0.0f;
+  // hardware reciprocal (1 ulp): the weight stays well inside the parity
+  // tolerance, and every path of the search uses this same function
+  const float inv = den > 0.0f ? __builtin_amdgcn_rcpf(den) : 0.0f;
   PairK k;
   k.e = make_float4(ex, ey, ez, 0.0f);
   k.ei = make_float4(ex * inv, ey * inv, ez * inv, inv);
@@ -237,14 +239,6 @@ struct GlobalWin {
     return make_float4(q[0], q[1], q[2], 1.0f);
   }
 };
-
-__device__ __forceinline__ void pair_from_index(int p, int& i, int& j) {
-  int jj = (int)((1.0f + sqrtf(1.0f + 8.0f * (float)p)) * 0.5f);
-  while (jj * (jj - 1) / 2 > p) --jj;
-  while ((jj + 1) * jj / 2 <= p) ++jj;
-  j = jj;
-  i = p - jj * (jj - 1) / 2;
-}
 
 // ---------------------------------------------------------------------------
 // Exhaustive search of one strip (Eq. 3 with Eq. 4 over all pairs)
@@ -666,17 +660,29 @@ __device__ __forceinline__ void search_tile(const ImgDesc& d, int ty, int tx, fl
     }
   }
   __syncthreads();
-  if (MODE == MODE_EXH && TABLE) {
-    const int np = n_pairs(K2);
-    const int total = tqy * tqx * np;
-    for (int e = threadIdx.x; e < total; e += kThreads) {
-      const int c = e / np, pr = e - c * np;
-      int i, j;
-      pair_from_index(pr, i, j);
-      const int cy = c / tqx, cx = c - cy * tqx;
-      const float4 Li = sL[(cy + i / kw) * lx + cx + i % kw];
-      const float4 Lj = sL[(cy + j / kw) * lx + cx + j % kw];
-      sTab[c * tstride + pr] = pair_consts(Li, Lj, eps);
+  if constexpr (MODE == MODE_EXH && TABLE) {
+    // the table exists for 3 x 3 windows: 36 pairs per centre
+    static_assert(KW == 3, "the pair table is built for 3 x 3 windows");
+    constexpr int NP = 36;
+    constexpr int kBuild = (kThreads / NP) * NP;  // 252 threads: each keeps one pair index
+    const int ncent = tqy * tqx;
+    const int tid = (int)threadIdx.x;
+    if (tid < kBuild) {
+      const int pr = tid % NP;
+      // colexicographic pair pr = j (j - 1) / 2 + i, i < j
+      const int j = 1 + (pr >= 1) + (pr >= 3) + (pr >= 6) + (pr >= 10) + (pr >= 15) + (pr >= 21) + (pr >= 28);
+      const int i = pr - ((j * (j - 1)) >> 1);
+      // window offset o -> (o / 3, o % 3) for o < 9, as LDS offsets
+      const int iy = (i * 11) >> 5, jy = (j * 11) >> 5;
+      const int offi = iy * lx + i - 3 * iy, offj = jy * lx + j - 3 * jy;
+      const float inv_tqx = __builtin_amdgcn_rcpf((float)tqx);
+      for (int c = tid / NP; c < ncent; c += kBuild / NP) {
+        // centre (cy, cx) of the tile: c / tqx, exact for c < 2^16
+        const int cy = (int)(((float)c + 0.5f) * inv_tqx), cx = c - cy * tqx;
+        const float4 Li = sL[cy * lx + cx + offi];
+        const float4 Lj = sL[cy * lx + cx + offj];
+        sTab[c * tstride + pr] = pair_consts(Li, Lj, eps);
+      }
     }
     __syncthreads();
   }

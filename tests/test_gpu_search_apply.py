@@ -98,6 +98,10 @@ CASES = [
     (30, 45, 2, 3, 1, "fast", "f16"),
     (40, 72, 4, 3, 4, "fast", "f16"),
     (40, 72, 4, 3, 2, "exhaustive", "f16"),
+    (128, 192, 32, 3, 3, "exhaustive", "f32"),
+    (300, 400, 64, 3, 3, "exhaustive", "f32"),
+    (260, 520, 128, 3, 3, "fast", "f32"),
+    (200, 200, 64, 5, 1, "fast", "f32"),
 ]
 
 
