@@ -63,6 +63,7 @@ __all__ = [
     "window_cells",
     "search_exhaustive",
     "search_fast",
+    "search_gnu",
     "search",
     "apply",
     "apply_backward",
@@ -298,12 +299,40 @@ def search_fast(I, L, s, k=WINDOW, eps=EPS, pixels=None) -> SearchResult:
     return SearchResult(a=a, b=b, alpha=omega, err=best, pixels=None if pixels is None else np.asarray(pixels))
 
 
+def search_gnu(I, L, s, k=WINDOW, pixels=None) -> SearchResult:
+    """Guided nearest-neighbour upsampling (GNU, Sec. 3.2), the omega = 1
+    special case of the model: a = b = the window cell of least Euclidean
+    colour distance to I_p (first in ascending LR index on ties), weight 1,
+    err = that distance."""
+    I = np.asarray(I, dtype=np.float64)
+    L = np.asarray(L, dtype=np.float64)
+    H, W = I.shape[:2]
+    h, w = L.shape[:2]
+    if (h, w) != lr_shape(H, W, s):
+        raise ValueError("I_low must be ceil(H/s) x ceil(W/s)")
+    ys, xs = _pixel_coords(H, W, pixels)
+    Ip = I[ys, xs]
+    Lf = L.reshape(-1, L.shape[2])
+    n = Ip.shape[0]
+    da = np.full(n, np.inf)
+    a = np.full(n, -1, dtype=np.int64)
+    for v, lin in _candidates(ys, xs, s, h, w, k):
+        d = Ip - Lf[lin]
+        dd = np.where(v, np.sqrt(np.einsum("nc,nc->n", d, d)), np.inf)
+        upd = dd < da
+        da = np.where(upd, dd, da)
+        a = np.where(upd, lin, a)
+    return SearchResult(a=a, b=a.copy(), alpha=np.ones(n), err=da, pixels=None if pixels is None else np.asarray(pixels))
+
+
 def search(I, L, s, k=WINDOW, eps=EPS, mode="exhaustive", pixels=None) -> SearchResult:
     if mode == "exhaustive":
         return search_exhaustive(I, L, s, k, eps, pixels)
     if mode == "fast":
         return search_fast(I, L, s, k, eps, pixels)
-    raise ValueError("mode must be 'exhaustive' or 'fast'")
+    if mode == "gnu":
+        return search_gnu(I, L, s, k, pixels)
+    raise ValueError("mode must be 'exhaustive', 'fast' or 'gnu'")
 
 
 # --------------------------------------------------------------------------

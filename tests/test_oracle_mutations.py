@@ -49,6 +49,9 @@ MUTATIONS = [
      "            for dy, dx in ((-1, 0), (1, 0), (0, -1), (0, 1)):\n                if True:\n                    ny, nx"),
     ("regular grid samples the block corner", "ys = np.minimum(np.arange(h) * s + s // 2, H - 1)",
      "ys = np.minimum(np.arange(h) * s, H - 1)"),
+    ("GNU weight on the wrong endpoint", "alpha=np.ones(n), err=da", "alpha=np.zeros(n), err=da"),
+    ("GNU takes the farthest colour", "        upd = dd < da\n        da = np.where(upd, dd, da)\n        a = np.where(upd, lin, a)",
+     "        upd = dd > da\n        da = np.where(upd, dd, da)\n        a = np.where(upd, lin, a)"),
     ("gradient step uphill", "        Z = L - eta * D\n", "        Z = L + eta * D\n"),
     ("loss gradient without its factor 2", "    G = 2.0 * (I_hat - I)\n", "    G = (I_hat - I)\n"),
     ("snap keeps the last nearest pixel", "            p = int(members[int(np.argmin(dist))])  # first minimum",
@@ -86,6 +89,7 @@ def _pins():
         lambda: P.test_snap_to_block_bruteforce(),
         lambda: P.test_gradient_joint_fixed_points(),
         lambda: P.test_gradient_joint_best_and_copies(),
+        lambda: P.test_gnu_is_the_nearest_window_colour(),
     ]
 
 

@@ -657,3 +657,34 @@ def test_gradient_joint_best_and_copies():
         for qx in range(w):
             blk = If[qy * s : qy * s + s, qx * s : qx * s + s].reshape(-1, 3)
             assert np.any(np.all(blk == r.L[qy, qx], axis=1))
+
+
+def test_gnu_is_the_nearest_window_colour():
+    """GNU (Sec. 3.2): per pixel the nearest colour of the truncated window by
+    an independent double loop (first on ties), weight 1, err its distance;
+    the GLU searches never do worse, and GNU's a is fast mode's anchor."""
+    s, k = 4, 3
+    I = synth.voronoi(20, 24, n_cells=6, n_dots=2, dot_px=(1, 2), seed=13).astype(np.float64)
+    L = O.downsample_point(I, s)
+    L[1, 2] = L[1, 1]  # an exact colour tie inside some windows
+    g = O.search_gnu(I, L, s, k)
+    H, W = I.shape[:2]
+    h, w = L.shape[:2]
+    for y in range(H):
+        for x in range(W):
+            best, arg = None, None
+            for cy in range(max(0, y // s - 1), min(h, y // s + 2)):
+                for cx in range(max(0, x // s - 1), min(w, x // s + 2)):
+                    dd = math.sqrt(sum((I[y, x, c] - L[cy, cx, c]) ** 2 for c in range(3)))
+                    if best is None or dd < best:
+                        best, arg = dd, cy * w + cx
+            p = y * W + x
+            assert g.a[p] == arg and g.b[p] == arg and g.alpha[p] == 1.0
+            assert abs(g.err[p] - best) <= 1e-12
+    ex = O.search_exhaustive(I, L, s, k)
+    fa = O.search_fast(I, L, s, k)
+    assert np.all(ex.err <= g.err + 1e-12) and np.all(fa.err <= g.err + 1e-12)
+    np.testing.assert_array_equal(fa.a, g.a)
+    # GNU upsampling copies the target of the anchor cell
+    T = np.random.default_rng(1).uniform(0, 1, (h, w, 2))
+    np.testing.assert_array_equal(O.apply(g.a, g.b, g.alpha, T), T.reshape(-1, 2)[g.a])
