@@ -479,6 +479,36 @@ def _configs(np, torch, synth, glu, dev, stream, scene):
     out["sweep_4k"] = sweep
     print("sweep done", file=sys.stderr, flush=True)
 
+    # quality on the 4K frame (synthetic analogue of the paper's comparisons):
+    # PSNR of T_hat against the LR operator applied at full resolution, f1(I),
+    # for GLU (both searches), GNU, GLU on the joint-downsampled guides, and
+    # bilinear upsampling of T_low; and self-upsampling PSNR (T = I) per window
+    def psnr(a, b):
+        mse = float(((a.double() - b.double()) ** 2).mean())
+        return round(10.0 * np.log10(1.0 / mse), 3) if mse > 0 else float("inf")
+
+    target = _lr_f1_torch(torch, I)
+    q = {}
+    for mode in ("exhaustive", "fast", "gnu"):
+        o, _ = glu.search_apply(I, Il8, T8, 8, 3, EPS, mode, store_theta=False)
+        q["glu_" + mode if mode != "gnu" else "gnu"] = psnr(o, target)
+    Lj, _, _, _, _ = glu.joint_downsample(I, Il8, 8, 3, EPS, "exhaustive", max_iter=5, log_capacity=0)
+    o, _ = glu.search_apply(I, Lj, _lr_f1_torch(torch, Lj).contiguous(), 8, 3, EPS, "exhaustive", store_theta=False)
+    q["glu_exhaustive_alg2_5rounds"] = psnr(o, target)
+    Lg, _, _, _, _ = glu.joint_downsample_grad(I, Il8, 8, 3, EPS, "exhaustive", eta=0.01, n_steps=5)
+    o, _ = glu.search_apply(I, Lg, _lr_f1_torch(torch, Lg).contiguous(), 8, 3, EPS, "exhaustive", store_theta=False)
+    q["glu_exhaustive_gradient_5steps"] = psnr(o, target)
+    up = torch.nn.functional.interpolate(T8.permute(2, 0, 1).unsqueeze(0), size=(H, W), mode="bilinear",
+                                         align_corners=False)[0].permute(1, 2, 0)
+    q["bilinear"] = psnr(up, target)
+    selfp = {}
+    for kk in (3, 5, 7, 9):
+        o, _ = glu.search_apply(I, Il8, Il8, 8, kk, EPS, "exhaustive", store_theta=False)
+        selfp[str(kk)] = psnr(o, I)
+    q["self_upsampling_by_window"] = selfp
+    out["quality_4k_x8_psnr_db"] = q
+    print("quality done", file=sys.stderr, flush=True)
+
     # uneven batch: 64 images, sizes 720x480 .. 6000x4000, s in {4, 8, 16},
     # k in {3, 5}; crops of one seeded canvas with the same cell density
     specs = synth.uneven_batch_specs(64, seed=4)

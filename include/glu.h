@@ -73,8 +73,10 @@ typedef enum { GLU_F32 = 0, GLU_F16 = 1 } glu_dtype;
 
 /* GLU_SEARCH_EXHAUSTIVE: every pair of the window with the projection weight
  * of Eq. 4 clamped to [0, 1] (Sec. 3.1); GLU_SEARCH_FAST: Algorithm 1 with
- * the weight of Eq. 5 (Sec. 3.2). */
-typedef enum { GLU_SEARCH_EXHAUSTIVE = 0, GLU_SEARCH_FAST = 1 } glu_mode;
+ * the weight of Eq. 5 (Sec. 3.2); GLU_SEARCH_GNU: guided nearest-neighbour
+ * upsampling, the weight-1 special case of Sec. 3.2 (a = b = the window cell
+ * of nearest colour, first in LR index on ties; E = that distance). */
+typedef enum { GLU_SEARCH_EXHAUSTIVE = 0, GLU_SEARCH_FAST = 1, GLU_SEARCH_GNU = 2 } glu_mode;
 
 /* Regular-grid downsampling keeps one HR pixel per LR pixel (Sec. 3.1,
  * Sec. 3.3); BOX averages the in-image pixels of each s x s block. */

@@ -60,7 +60,7 @@ glu_status check_params(const glu_params* p) {
   if (p->k < 1 || p->k > kMaxK || (p->k % 2) == 0)
     return fail(GLU_ERR_PARAM, "k = %d must be odd in 1..%d", p->k, kMaxK);
   if (!(p->eps >= 0.0f) || !std::isfinite(p->eps)) return fail(GLU_ERR_PARAM, "eps must be finite and >= 0");
-  if (p->mode != GLU_SEARCH_EXHAUSTIVE && p->mode != GLU_SEARCH_FAST)
+  if (p->mode != GLU_SEARCH_EXHAUSTIVE && p->mode != GLU_SEARCH_FAST && p->mode != GLU_SEARCH_GNU)
     return fail(GLU_ERR_PARAM, "unknown mode %d", (int)p->mode);
   if (p->flags != 0) return fail(GLU_ERR_PARAM, "flags must be 0");
   return GLU_OK;
@@ -278,10 +278,11 @@ static glu_status run_search(const glu_image* I, const glu_image* I_low, const g
   d.k = p->k;
   d.C = C;
   d.dtype = I->dtype;
-  const int mode = p->mode == GLU_SEARCH_FAST ? MODE_FAST : MODE_EXH;
+  const int mode = p->mode == GLU_SEARCH_EXHAUSTIVE ? MODE_EXH : MODE_FAST;
   const bool table = uses_pair_table(mode, p->k);
-  const TileChoice tc = choose_tile(p->s, p->k, mode, fused, table, tuned_variant(mode, p->k, p->s, I->dtype));
+  const TileChoice tc = choose_tile(p->s, p->k, mode, fused, table, tuned_variant(p->mode, p->k, p->s, I->dtype));
   fill_tiles(d, tc);
+  d.gnu = p->mode == GLU_SEARCH_GNU;
   d.vec = launch_vec_flags(d, tc.P, dtype_size(I->dtype));
   const size_t lds = 16 * (size_t)search_tile_words(tc.tqy, tc.tqx, p->k, mode, fused, table);
   const int64_t ntiles = (int64_t)d.tiles_x * d.tiles_y;

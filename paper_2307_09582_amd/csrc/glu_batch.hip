@@ -192,9 +192,10 @@ static glu_status make_item(const glu_batch_item& it, const glu_params& p, int m
   d.C = it.T_low.channels;
   d.dtype = it.I.dtype;
   const bool table = uses_pair_table(mode, it.k);
-  const int var = variant_override >= 0 ? variant_override : tuned_variant(mode, it.k, it.s, it.I.dtype);
+  const int var = variant_override >= 0 ? variant_override : tuned_variant(p.mode, it.k, it.s, it.I.dtype);
   const TileChoice tc = choose_tile(it.s, it.k, mode, true, table, var);
   fill_tiles(d, tc);
+  d.gnu = p.mode == GLU_SEARCH_GNU;
   d.vec = launch_vec_flags(d, tc.P, dtype_size((glu_dtype)it.I.dtype));
   d.variant = kernel_variant(it.k, tc.P, mode, it.I.dtype);
   lds = 16 * (size_t)search_tile_words(tc.tqy, tc.tqx, it.k, mode, true, table);
@@ -213,7 +214,7 @@ static glu_status plan_build(const glu_batch_item* items, int32_t n, const glu_p
   base.s = 1;
   base.k = 3;
   if ((st = check_params(&base))) return st;
-  const int mode = p->mode == GLU_SEARCH_FAST ? MODE_FAST : MODE_EXH;
+  const int mode = p->mode == GLU_SEARCH_EXHAUSTIVE ? MODE_EXH : MODE_FAST;
   std::vector<ImgDesc> all;
   std::vector<size_t> all_lds;
   all.reserve(n);
@@ -333,7 +334,7 @@ glu_status glu_batch_plan_info(const glu_batch_plan* plan, int64_t* n_tiles, int
 glu_status glu_autotune(const glu_batch_item* item, const glu_params* p, int32_t* chosen, void* stream) {
   clear_error();
   if (!item || !p) return fail(GLU_ERR_NULL, "item/params is NULL");
-  const int mode = p->mode == GLU_SEARCH_FAST ? MODE_FAST : MODE_EXH;
+  const int mode = p->mode == GLU_SEARCH_EXHAUSTIVE ? MODE_EXH : MODE_FAST;
   hipStream_t sm = (hipStream_t)stream;
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
@@ -362,7 +363,7 @@ glu_status glu_autotune(const glu_batch_item* item, const glu_params* p, int32_t
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   if (st) return st;
-  set_tuned_variant(mode, item->k, item->s, item->I.dtype, best);
+  set_tuned_variant(p->mode, item->k, item->s, item->I.dtype, best);
   if (chosen) *chosen = best;
   return GLU_OK;
 }

@@ -412,7 +412,7 @@ __device__ __forceinline__ float exh_alpha(const float (&ip)[3], const Win& win,
 // keeping the first b of least error.
 template <int KW, int P, bool BORDER, typename Win>
 __device__ __forceinline__ void fast_strip(const float (&ip)[P][3], const Win& win,
-                                           float eps, int kw_rt, float (&best)[P], int (&code)[P],
+                                           float eps, int kw_rt, bool gnu, float (&best)[P], int (&code)[P],
                                            float (&alpha)[P]) {
   constexpr int kUnrollJ = KW == 3 ? 9 : 1;
   const int kw = KW > 0 ? KW : kw_rt;
@@ -439,6 +439,16 @@ __device__ __forceinline__ void fast_strip(const float (&ip)[P][3], const Win& w
       dmin[q] = lt ? D : dmin[q];
       ia[q] = lt ? j : ia[q];
     }
+  }
+  if (gnu) {
+    // guided nearest neighbour: the anchor alone, weight 1 (uniform branch)
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+      best[q] = dmin[q];
+      code[q] = ia[q] * K2 + ia[q];
+      alpha[q] = 1.0f;
+    }
+    return;
   }
   float La[P][3], sa[P], omb[P];
 #pragma unroll
@@ -728,9 +738,9 @@ __device__ __forceinline__ void search_tile(const ImgDesc& d, int ty, int tx, fl
       }
     } else {
       if (interior)
-        fast_strip<KW, P, false>(ip, win, eps, kw, best, code, al);
+        fast_strip<KW, P, false>(ip, win, eps, kw, d.gnu != 0, best, code, al);
       else
-        fast_strip<KW, P, true>(ip, win, eps, kw, best, code, al);
+        fast_strip<KW, P, true>(ip, win, eps, kw, d.gnu != 0, best, code, al);
     }
     float e[P];
 #pragma unroll

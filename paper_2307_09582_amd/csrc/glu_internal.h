@@ -43,6 +43,7 @@ struct ImgDesc {
   uint32_t vec;         // VEC_* flags
   int32_t dtype;        // glu_dtype of I, L, T, That
   int32_t variant;      // kernel variant index (batched dispatch)
+  int32_t gnu;          // fast-mode kernels: stop after the anchor (GNU)
   int64_t tile_begin;   // first global tile index of this image (batched)
 };
 

@@ -226,6 +226,7 @@ struct JdTrialArgs {
   int64_t th_stride;
   JdBuffers b;
   int H, W, h, w, s, k, mode;
+  int gnu;  // GNU: fast-mode anchor only
   float eps;
   int comp_begin;  // first component (in schedule order) of this launch
 };
@@ -257,7 +258,7 @@ __device__ __forceinline__ void search_one(const JdTrialArgs& a, int y, int x, i
     exh_strip<0, 1, true, false>(ip, win, nullptr, a.eps, a.k, best, cd);
     alp[0] = exh_alpha<0, false>(ip[0], win, nullptr, a.eps, a.k, cd[0]);
   } else {
-    fast_strip<0, 1, true>(ip, win, a.eps, a.k, best, cd, alp);
+    fast_strip<0, 1, true>(ip, win, a.eps, a.k, a.gnu != 0, best, cd, alp);
   }
   code = cd[0];
   al = alp[0];
@@ -655,7 +656,8 @@ glu_status glu_joint_downsample(const glu_image* I, glu_image* I_low, const glu_
     ta.w = w;
     ta.s = s;
     ta.k = p->k;
-    ta.mode = p->mode == GLU_SEARCH_FAST ? MODE_FAST : MODE_EXH;
+    ta.mode = p->mode == GLU_SEARCH_EXHAUSTIVE ? MODE_EXH : MODE_FAST;
+    ta.gnu = p->mode == GLU_SEARCH_GNU;
     ta.eps = p->eps;
     for (int lv = 1; lv <= max_level; ++lv) {
       const int a0 = lvl_start[lv], a1 = lvl_start[lv + 1];

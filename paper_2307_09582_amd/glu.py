@@ -19,7 +19,7 @@ EPS = 1e-3  # Eq. 4 regulariser (Sec. 3.1)
 TAU = 30.0 / 255.0  # error threshold of Algorithm 2 (Sec. 5.2)
 N_ITER = 3  # iterations of Algorithm 2 (Sec. 5.2)
 
-_MODES = {"exhaustive": L.GLU_SEARCH_EXHAUSTIVE, "fast": L.GLU_SEARCH_FAST}
+_MODES = {"exhaustive": L.GLU_SEARCH_EXHAUSTIVE, "fast": L.GLU_SEARCH_FAST, "gnu": L.GLU_SEARCH_GNU}
 
 
 @dataclass
@@ -73,7 +73,7 @@ def _theta(th: Theta) -> L.glu_theta:
 
 def _params(s: int, k: int, eps: float, mode: str = "exhaustive") -> L.glu_params:
     if mode not in _MODES:
-        raise ValueError("mode must be 'exhaustive' or 'fast'")
+        raise ValueError("mode must be 'exhaustive', 'fast' or 'gnu'")
     return L.glu_params(int(s), int(k), float(eps), _MODES[mode], 0)
 
 

@@ -7,7 +7,7 @@ Per pixel (exhaustive mode):
      squared); alpha is then checked against the oracle's weight for the
      GPU's pair.
 Fast mode applies rule 2 first to the anchor (colour-distance gap), then to
-b given the GPU's anchor.  E (when returned) must match the oracle's error
+b given the GPU's anchor; GNU mode to its anchor (b = a, weight 1).  E (when returned) must match the oracle's error
 of the GPU's pair to 1e-6, and T_hat the oracle's Eq. 1 with the GPU's
 pair and the oracle's weight for it to 1e-5 (float32) or one half-precision
 ulp + 1e-5 (float16).
@@ -80,7 +80,19 @@ def check_search(I, L, s, k, eps, mode, code, alpha, err=None, pixels=None, T_lo
     assert _in_window(a_g, pixels, W, s, k, h, w).all() and _in_window(b_g, pixels, W, s, k, h, w).all()
     al_g = np.asarray(alpha, dtype=np.float64).reshape(-1)[pixels]
     ref = O.search(I, L, s, k, eps, mode, pixels=pixels)
-    if mode == "exhaustive":
+    if mode == "gnu":
+        # the anchor alone: a near-tie of the nearest colour, b = a, weight 1
+        Lf = np.asarray(L, dtype=np.float64).reshape(-1, 3)
+        ys, xs = np.divmod(pixels, W)
+        Ip = np.asarray(I, dtype=np.float64)[ys, xs]
+        d_g = np.linalg.norm(Ip - Lf[a_g], axis=1)
+        gap = d_g - ref.err
+        assert not (gap > TIE_TOL).any(), "non-tie GNU anchor, worst gap %.3g" % float(gap.max())
+        assert np.array_equal(a_g, b_g) and np.all(al_g == 1.0)
+        rep["near_ties"] = int((a_g != ref.a).sum())
+        al_ref = np.ones_like(al_g)
+        e_ref = d_g
+    elif mode == "exhaustive":
         assert np.all(a_g <= b_g), "exhaustive codes must have a <= b"
         same = (a_g == ref.a) & (b_g == ref.b)
         al_ref = np.where(same, ref.alpha, 0.0)

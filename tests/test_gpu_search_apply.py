@@ -295,3 +295,23 @@ def test_apply_random_theta(H, W, s, k, C, dt, pad, off):
         assert np.isnan(rest[:, :off]).all()
     if pad:
         assert np.isnan(rest[:, off + W:]).all()
+
+
+@pytest.mark.parametrize("H,W,s,k,C,dt", [(200, 264, 8, 3, 3, "f32"), (37, 53, 4, 5, 1, "f32"), (29, 31, 3, 3, 3, "f16"),
+                                           (41, 39, 4, 7, 2, "f32")])
+def test_gnu_mode(H, W, s, k, C, dt):
+    """GNU (nearest window colour, weight 1) through search, apply, the fused
+    pass and a batch plan."""
+    glu = _glu()
+    log_case(test="gnu", H=H, W=W, s=s, k=k, C=C, dt=dt)
+    I, L, T = _inputs(H, W, s, seed=H + W + 5, n_cells=max(4, H * W // 400), n_dots=3, C=C)
+    dtype = torch.float16 if dt == "f16" else torch.float32
+    _run_and_check(glu, I, L, T, s, k, "gnu", dtype=dtype)
+    npd = np.float16 if dt == "f16" else np.float32
+    it = dict(I=dev(I.astype(npd)), I_low=dev(L.astype(npd)), T_low=dev(T.astype(npd)), s=s, k=k,
+              T_hat=torch.empty((H, W, C), dtype=dtype, device="cuda"))
+    plan = glu.BatchPlan([it], mode="gnu")
+    plan.launch()
+    out, _ = glu.search_apply(it["I"], it["I_low"], it["T_low"], s, k, mode="gnu")
+    assert torch.equal(out, it["T_hat"])
+    plan.close()
