@@ -245,7 +245,7 @@ def main():
     kern = {}
     other = "fast" if args.mode == "exhaustive" else "exhaustive"
     if args.only == "all":
-        for mode in (args.mode, other):
+        for mode in (args.mode, other, "gnu"):
             kern[mode] = dict(
                 search_us=1e3 * _events_ms(torch, stream, search_only(mode), args.steps, 20),
                 apply_us=1e3 * _events_ms(torch, stream, apply_only(mode), args.steps, 20),
@@ -508,6 +508,146 @@ def _configs(np, torch, synth, glu, dev, stream, scene):
     q["self_upsampling_by_window"] = selfp
     out["quality_4k_x8_psnr_db"] = q
     print("quality done", file=sys.stderr, flush=True)
+
+    # target-free overlap: the search does not depend on the LR target, so
+    # for video it runs on one stream while the LR operator of the same frame
+    # runs on another, and the apply joins them.  The operator stands in for
+    # an LR network: four 3x3 convolutions (3-32-32-32-3 channels) at 480x270.
+    torch.manual_seed(9)
+    convs = [torch.nn.Conv2d(ci, co, 3, padding=1).to(dev).half()
+             for ci, co in ((3, 32), (32, 32), (32, 32), (32, 3))]
+
+    def lr_op(x):
+        y = x.permute(2, 0, 1).unsqueeze(0)
+        for i, cv in enumerate(convs):
+            y = cv(y)
+            if i < len(convs) - 1:
+                y = torch.relu(y)
+        return torch.sigmoid(y)[0].permute(1, 2, 0).contiguous()
+
+    canvas = torch.from_numpy(scene.canvas.astype(np.float32)).to(dev)
+    nf = 24
+    frames = [_noisy_crop(torch, canvas, 0, 3 * t, H, W, 9000 + t, torch.float16) for t in range(nf)]
+    del canvas
+    lows = [torch.empty((H // S, W // S, 3), dtype=torch.float16, device=dev) for _ in range(nf)]
+    targets = [None] * nf
+    thetas = [glu.empty_theta(H, W, dev) for _ in range(nf)]
+    outs = [torch.empty((H, W, 3), dtype=torch.float16, device=dev) for _ in range(nf)]
+    side = torch.cuda.Stream()  # default priority
+
+    def down(t):
+        lows[t] = glu.downsample(frames[t], S, "point")
+
+    def sequential():
+        for t in range(nf):
+            down(t)
+            targets[t] = lr_op(lows[t])
+            glu.search_apply(frames[t], lows[t], targets[t], S, K, EPS, "exhaustive", theta=thetas[t], out=outs[t])
+
+    def overlapped():
+        main = torch.cuda.current_stream()
+        done = [torch.cuda.Event() for _ in range(nf)]
+        for t in range(nf):
+            down(t)
+            ev = torch.cuda.Event()
+            ev.record(main)
+            side.wait_event(ev)
+            with torch.cuda.stream(side):
+                targets[t] = lr_op(lows[t])
+                done[t].record(side)
+            glu.search(frames[t], lows[t], S, K, EPS, "exhaustive", theta=thetas[t])
+            if t > 0:  # the previous frame's apply, behind this frame's search
+                main.wait_event(done[t - 1])
+                glu.apply(thetas[t - 1], targets[t - 1], S, K, out=outs[t - 1])
+        main.wait_event(done[nf - 1])
+        glu.apply(thetas[nf - 1], targets[nf - 1], S, K, out=outs[nf - 1])
+
+    with torch.no_grad():
+        down(0)
+        ms_op = _events_ms(torch, stream, lambda i: lr_op(lows[0]), 50, 5)
+        ms_seq = _events_ms(torch, stream, lambda i: sequential(), 3, 1)
+        ms_ovl = _events_ms(torch, stream, lambda i: overlapped(), 3, 1)
+        ovl_out = [o.clone() for o in outs]
+        sequential()
+        torch.cuda.synchronize()
+        ref = [o.clone() for o in outs]
+        same = all(torch.equal(a, b) for a, b in zip(ref, ovl_out))
+        del ovl_out
+
+        # the same two pipelines captured as graphs (the side stream joins the
+        # capture through the events), which takes host launch cost out; each
+        # replay is checked against the eager result, with eager work between
+        graphs, replay_ok = {}, True
+        for name, fn in (("sequential", sequential), ("overlapped", overlapped)):
+            s0 = torch.cuda.Stream()
+            s0.wait_stream(stream)
+            with torch.cuda.stream(s0):
+                fn()
+            stream.wait_stream(s0)
+            torch.cuda.synchronize()
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g):
+                fn()
+            for rep in range(3):
+                for o in outs:
+                    o.zero_()
+                g.replay()
+                torch.cuda.synchronize()
+                replay_ok &= all(torch.equal(a, b) for a, b in zip(ref, outs))
+                lr_op(lows[0]).sum().item()
+            graphs[name] = g
+        ms_gseq = _events_ms(torch, stream, lambda i: graphs["sequential"].replay(), 10, 2)
+        ms_govl = _events_ms(torch, stream, lambda i: graphs["overlapped"].replay(), 10, 2)
+        del graphs
+
+        # latency of one frame on an idle GPU, from its downsample to its
+        # last T_hat write; the overlapped form submits the search first
+        def one_seq(t):
+            down(t)
+            targets[t] = lr_op(lows[t])
+            glu.search_apply(frames[t], lows[t], targets[t], S, K, EPS, "exhaustive", theta=thetas[t], out=outs[t])
+
+        def one_ovl(t):
+            main = torch.cuda.current_stream()
+            down(t)
+            ev, done = torch.cuda.Event(), torch.cuda.Event()
+            ev.record(main)
+            glu.search(frames[t], lows[t], S, K, EPS, "exhaustive", theta=thetas[t])
+            side.wait_event(ev)
+            with torch.cuda.stream(side):
+                targets[t] = lr_op(lows[t])
+                done.record(side)
+            main.wait_event(done)
+            glu.apply(thetas[t], targets[t], S, K, out=outs[t])
+
+        lat, lat_ok = {}, True
+        for name, fn in (("sequential", one_seq), ("overlapped", one_ovl)):
+            fn(0)
+            torch.cuda.synchronize()
+            us = []
+            for t in range(nf):
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record(stream)
+                fn(t)
+                b.record(stream)
+                torch.cuda.synchronize()
+                us.append(1e3 * a.elapsed_time(b))
+            us.sort()
+            lat[name] = {"median_us": round(us[nf // 2], 1), "p90_us": round(us[(9 * nf) // 10], 1)}
+            lat_ok &= all(torch.equal(x, y) for x, y in zip(ref, outs))
+    out["video_overlap_4k_f16"] = {
+        "frames": nf, "lr_operator_us": round(1e3 * ms_op, 1),
+        "eager": {"sequential_ms": round(ms_seq, 3), "overlapped_ms": round(ms_ovl, 3),
+                  "sequential_fps": round(nf / (ms_seq * 1e-3), 1), "overlapped_fps": round(nf / (ms_ovl * 1e-3), 1)},
+        "graph": {"sequential_ms": round(ms_gseq, 3), "overlapped_ms": round(ms_govl, 3),
+                  "sequential_fps": round(nf / (ms_gseq * 1e-3), 1),
+                  "overlapped_fps": round(nf / (ms_govl * 1e-3), 1)},
+        "latency_one_frame": lat,
+        "outputs_equal": same, "graph_replays_equal": replay_ok, "latency_runs_equal": lat_ok,
+    }
+    del frames, lows, targets, thetas, outs
+    torch.cuda.synchronize()
+    print("overlap done", file=sys.stderr, flush=True)
 
     # uneven batch: 64 images, sizes 720x480 .. 6000x4000, s in {4, 8, 16},
     # k in {3, 5}; crops of one seeded canvas with the same cell density
