@@ -66,6 +66,9 @@ def _parse():
     ap.add_argument("--only", choices=["all", "step"], default="all",
                     help="'step' times only the headline step (for profiling)")
     ap.add_argument("--no-configs", action="store_true", help="skip the further workloads")
+    ap.add_argument("--kernel-modes", default="exhaustive,fast,gnu",
+                    help="search modes of the per-kernel timings (fast and gnu share the fast kernels, so a "
+                         "kernel trace that should tell them apart times one of them)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (a known-size reference for HBM counters)")
     return ap.parse_args()
@@ -243,9 +246,11 @@ def main():
     dist = _per_launch_us(torch, stream, step, 200, 20) if args.only == "all" else None
 
     kern = {}
-    other = "fast" if args.mode == "exhaustive" else "exhaustive"
     if args.only == "all":
-        for mode in (args.mode, other, "gnu"):
+        modes = [m for m in args.kernel_modes.split(",") if m]
+        if args.mode not in modes:
+            raise SystemExit("--kernel-modes must include --mode")
+        for mode in modes:
             kern[mode] = dict(
                 search_us=1e3 * _events_ms(torch, stream, search_only(mode), args.steps, 20),
                 apply_us=1e3 * _events_ms(torch, stream, apply_only(mode), args.steps, 20),
@@ -475,6 +480,15 @@ def _configs(np, torch, synth, glu, dev, stream, scene):
             ms = _events_ms(torch, stream,
                             lambda i: glu.search_apply(I, Ils, Ts, ss, 3, EPS, mode, theta=thw, out=ow), 20, 5)
             row[mode] = {"us": round(1e3 * ms, 1), "Mpx_s": round(H * W / (ms * 1e-3) / 1e6, 1)}
+        # backward of the apply with the Theta just written, both gradients
+        Gs = torch.randn((H, W, 3), dtype=torch.float32, device=dev, generator=torch.Generator(dev).manual_seed(6))
+        wss = torch.empty(glu.apply_backward_workspace(H, W, 3, ss, 3) // 4 + 1, dtype=torch.float32, device=dev)
+        gTs = torch.empty_like(Ts)
+        gas = torch.empty((H, W), dtype=torch.float32, device=dev)
+        ms = _events_ms(torch, stream, lambda i: glu.apply_backward(thw, Ts, Gs, ss, 3, workspace=wss, out_T_low=gTs,
+                                                                    out_alpha=gas), 20, 5)
+        row["backward"] = {"us": round(1e3 * ms, 1), "Mpx_s": round(H * W / (ms * 1e-3) / 1e6, 1)}
+        del Gs, wss
         sweep["s_at_k3"][str(ss)] = row
     out["sweep_4k"] = sweep
     print("sweep done", file=sys.stderr, flush=True)

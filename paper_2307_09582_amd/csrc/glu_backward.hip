@@ -10,13 +10,17 @@
 //
 //   pass 1 (HR stream, one read of G and Theta): for every LR cell c and
 //     every window offset o, S[o][c] = sum over the pixels of c's s x s
-//     block, in raster order, of the part of their contribution aimed at the
-//     cell c + offset(o).  A workgroup owns nb consecutive cells of one LR
-//     row (nb * k^2 <= 256).  It stages the LR target cells its pixels can
-//     reach in LDS, streams chunks of its HR rows (vector loads; dL/dalpha
-//     computed from the staged cells and written on the way) into LDS, and
-//     then one lane per (cell, offset) scans the chunk's pixels of its cell
-//     in raster order without branches.
+//     block of the part of their contribution aimed at the cell
+//     c + offset(o).  dL/dalpha is computed from LR target cells staged in
+//     LDS and written on the way.  Two forms, both with fixed orders:
+//     * registers (3 x 3 windows, s a multiple of 4 up to 256): a lane
+//       owns a 4-pixel column of a cell's block and every fourth HR row of
+//       it, and keeps 9 C sums (window offset, channel) in registers; the
+//       lanes of a cell, then the four waves, add theirs in a fixed order.
+//     * scan (every other shape): a workgroup owns nb consecutive cells of
+//       one LR row (nb * k^2 <= 256), streams chunks of its HR rows into
+//       LDS, and one lane per (cell, offset) scans the chunk's pixels of
+//       its cell in raster order without branches.
 //   pass 2 (LR): dT_low[q] = sum over o in ascending order of
 //     S[o][q - offset(o)].  S is offset-major, so for each o neighbouring
 //     lanes read neighbouring cells.
@@ -323,6 +327,195 @@ static BwdKernel pick_bwd(bool f16, int P, int k, int C) {
   return P == 4 ? pick_bwd_k<float, 4>(k, C) : pick_bwd_k<float, 1>(k, C);
 }
 
+// Register form of pass 1 (k = 3, s = 4 cps <= 256).  A workgroup owns
+// nb = floor(256 / s) cells of LR row qy, a segment of nb s pixels of its s
+// HR rows.  Wave v takes the rows y0 + v + 4 i; lane l < nb cps the pixels
+// x0 + 4 l .. + 3 of them, all in cell l / cps.  Each lane keeps 9 C sums
+// in registers, one per window offset and channel: a pixel adds alpha G
+// where o_a = o and (1 - alpha) G where o_b = o.  The first lane of a cell
+// adds up the sums of its cps lanes (cross-lane reads in a fixed order),
+// the four waves' sums meet in LDS, and one lane per (offset, cell) adds
+// them in wave order and writes S.
+constexpr int kRegWaves = kThreads / 64;
+
+// LDS float4 words of the register form: LR target cells (3 rows of nb + 2),
+// the code table (81 uint2), then the waves' sums (4 waves x nb cells x 9 C
+// floats, at most 4 x 64 x 9 float4).
+__host__ __device__ inline int reg_lds_words(int nb, int C) {
+  return 3 * (nb + 2) + (81 * 2 + 3) / 4 + (kRegWaves * nb * 9 * C + 3) / 4;
+}
+
+template <typename T, int C>
+__global__ __launch_bounds__(kThreads) void k_bwd_reg(const BwdArgs a0) {
+  extern __shared__ float4 smem[];
+  const BwdArgs a = batch_image<T>(a0);
+  const int s = a.s, cps = s >> 2, nb = a.nb;
+  const int qy = blockIdx.x / a.groups_x;
+  const int qx0 = (blockIdx.x - qy * a.groups_x) * nb;
+  const int lx = nb + 2;
+  float4* sT = smem;
+  uint2* sDec = reinterpret_cast<uint2*>(sT + 3 * lx);
+  float* sSum = reinterpret_cast<float*>(sT + 3 * lx + (81 * 2 + 3) / 4);
+  const int tid = (int)threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const T* __restrict__ TL = static_cast<const T*>(a.T);
+
+  // code -> (LDS offsets of the cells a and b relative to the pixel's cell
+  // at window offset 0, window offsets o_a and o_b)
+  for (int c = tid; c < 81; c += kThreads) {
+    const int oa = c / 9, ob = c - oa * 9;
+    sDec[c] = make_uint2((uint32_t)((oa / 3) * lx + oa % 3) | ((uint32_t)((ob / 3) * lx + ob % 3) << 16),
+                         (uint32_t)oa | ((uint32_t)ob << 16));
+  }
+  if (a.dalpha) {
+    // rows qy - 1 .. qy + 1, columns qx0 - 1 .. qx0 + nb, clamped to the LR
+    // image (codes from the search never leave it)
+    for (int i = tid; i < 3 * lx; i += kThreads) {
+      const int rr = i / lx, c = i - rr * lx;
+      const int cy = min(max(qy - 1 + rr, 0), a.h - 1);
+      const int cx = min(max(qx0 - 1 + c, 0), a.w - 1);
+      sT[i] = load_cell<T>(TL + (int64_t)cy * a.T_stride + (int64_t)cx * C, C);
+    }
+  }
+  __syncthreads();
+
+  const bool vecTh = (a.vec & VEC_THETA) != 0, vecG = (a.vec & VEC_G) != 0, vecA = (a.vec & VEC_T) != 0;
+  const int cl = lane / cps;
+  const int x = qx0 * s + 4 * lane;
+  const bool active = lane < nb * cps && x < a.W;  // x < W also keeps the cell inside the image
+  const bool full = x + 4 <= a.W;
+  float acc[9][C];
+#pragma unroll
+  for (int o = 0; o < 9; ++o)
+#pragma unroll
+    for (int ch = 0; ch < C; ++ch) acc[o][ch] = 0.f;
+
+  if (active) {
+    const int y1 = min(a.H, (qy + 1) * s);
+    for (int y = qy * s + wave; y < y1; y += kRegWaves) {
+      const int64_t to = (int64_t)y * a.th_stride + x;
+      int cd[4];
+      float al[4];
+      if (vecTh && full) {
+        const u32x2 c = __builtin_nontemporal_load(reinterpret_cast<const u32x2*>(a.code + to));
+        const f32x4 a4 = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(a.alpha + to));
+        cd[0] = c.x & 0xffff;
+        cd[1] = c.x >> 16;
+        cd[2] = c.y & 0xffff;
+        cd[3] = c.y >> 16;
+        al[0] = a4.x;
+        al[1] = a4.y;
+        al[2] = a4.z;
+        al[3] = a4.w;
+      } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const bool ok = full || (x + q < a.W);
+          cd[q] = ok ? a.code[to + q] : 0;
+          al[q] = ok ? a.alpha[to + q] : 0.f;
+        }
+      }
+      float g[4][4];
+      load_grad<4>(a.G + (int64_t)y * a.G_stride, x, a.W, C, vecG, full, g);  // zero past the image
+      float da[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const uint2 e = sDec[min(cd[q], 80)];
+        da[q] = 0.f;
+        if (a.dalpha) {
+          const float4 Ta = sT[cl + (e.x & 0xffff)];
+          const float4 Tb = sT[cl + (e.x >> 16)];
+          const float dv[4] = {Ta.x - Tb.x, Ta.y - Tb.y, Ta.z - Tb.z, Ta.w - Tb.w};
+          float v = g[q][0] * dv[0];
+#pragma unroll
+          for (int ch = 1; ch < C; ++ch) v = fmaf(g[q][ch], dv[ch], v);
+          da[q] = v;
+        }
+        if (a.S) {
+          const int oa = (int)(e.y & 0xffff), ob = (int)(e.y >> 16);
+#pragma unroll
+          for (int o = 0; o < 9; ++o) {
+            const float wt = (oa == o ? al[q] : 0.0f) + (ob == o ? 1.0f - al[q] : 0.0f);
+#pragma unroll
+            for (int ch = 0; ch < C; ++ch) acc[o][ch] = fmaf(wt, g[q][ch], acc[o][ch]);
+          }
+        }
+      }
+      if (a.dalpha) {
+        if (vecA && full) {
+          __builtin_nontemporal_store(f32x4{da[0], da[1], da[2], da[3]}, reinterpret_cast<f32x4*>(a.dalpha + to));
+        } else {
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            if (full || x + q < a.W) a.dalpha[to + q] = da[q];
+        }
+      }
+    }
+  }
+  if (!a.S) return;
+  // the first lane of each cell adds up its cps lanes (every lane takes part
+  // in the cross-lane reads): a butterfly when cps is a power of two, else
+  // in lane order
+  if ((cps & (cps - 1)) == 0) {
+    for (int m = 1; m < cps; m <<= 1) {
+#pragma unroll
+      for (int o = 0; o < 9; ++o)
+#pragma unroll
+        for (int ch = 0; ch < C; ++ch) acc[o][ch] += __shfl_xor(acc[o][ch], m, 64);
+    }
+  } else {
+    const int first = min(cl, nb - 1) * cps;
+#pragma unroll
+    for (int o = 0; o < 9; ++o)
+#pragma unroll
+      for (int ch = 0; ch < C; ++ch) {
+        float v = __shfl(acc[o][ch], first, 64);
+        for (int j = 1; j < cps; ++j) v += __shfl(acc[o][ch], first + j, 64);
+        acc[o][ch] = v;
+      }
+  }
+  if (lane < nb * cps && lane % cps == 0) {
+    float* dst = sSum + ((wave * nb + cl) * 9) * C;
+#pragma unroll
+    for (int o = 0; o < 9; ++o)
+#pragma unroll
+      for (int ch = 0; ch < C; ++ch) dst[o * C + ch] = acc[o][ch];
+  }
+  __syncthreads();
+  const int64_t hw = (int64_t)a.h * a.w;
+  const int nbv = min(nb, a.w - qx0);
+  for (int i = tid; i < 9 * nbv; i += kThreads) {
+    const int o = i / nbv, c = i - o * nbv;
+    float v[C];
+#pragma unroll
+    for (int ch = 0; ch < C; ++ch) v[ch] = 0.f;
+#pragma unroll
+    for (int wv = 0; wv < kRegWaves; ++wv)
+#pragma unroll
+      for (int ch = 0; ch < C; ++ch) v[ch] += sSum[((wv * nb + c) * 9 + o) * C + ch];
+    float* out = a.S + ((int64_t)o * hw + (int64_t)qy * a.w + qx0 + c) * C;
+#pragma unroll
+    for (int ch = 0; ch < C; ++ch) out[ch] = v[ch];
+  }
+}
+
+static BwdKernel pick_reg(bool f16, int C) {
+  switch (C) {
+    case 1: return f16 ? k_bwd_reg<__half, 1> : k_bwd_reg<float, 1>;
+    case 2: return f16 ? k_bwd_reg<__half, 2> : k_bwd_reg<float, 2>;
+    case 3: return f16 ? k_bwd_reg<__half, 3> : k_bwd_reg<float, 3>;
+    default: return f16 ? k_bwd_reg<__half, 4> : k_bwd_reg<float, 4>;
+  }
+}
+
+// The register form covers 3 x 3 windows with s a multiple of 4 up to
+// 256: the 64 lanes of a wave span nb = floor(256 / s) cells.
+static bool reg_geometry(int s, int k, int& nb) {
+  if (k != 3 || s % 4 != 0 || s > 256) return false;
+  nb = 256 / s;
+  return true;
+}
+
 template <int KW, int C>
 __global__ __launch_bounds__(256) void k_bwd_lr(const BwdArgs a0) {
   const BwdArgs a = batch_image<float>(a0);  // T is not read here
@@ -448,7 +641,8 @@ static glu_status backward_batched(int32_t n, const glu_batch_strides* bs, const
     a.b_dT = bs->grad_T_low;
     a.b_S = (int64_t)(glu_apply_backward_workspace(H, W, C, p) / sizeof(float));
   }
-  bwd_geometry(p->s, p->k, w, a.nb, a.rows_chunk);
+  const bool reg = reg_geometry(p->s, p->k, a.nb);
+  if (!reg) bwd_geometry(p->s, p->k, w, a.nb, a.rows_chunk);
   a.groups_x = ceil_div(w, a.nb);
   a.s_magic = (uint32_t)std::min<uint64_t>(0xffffffffull, (1ull << 32) / (uint64_t)p->s);
   const int P = (p->s % 4 == 0) ? 4 : 1;
@@ -465,11 +659,11 @@ static glu_status backward_batched(int32_t n, const glu_batch_strides* bs, const
       v |= VEC_G;
     a.vec = v;
   }
-  const size_t lds = (size_t)16 * bwd_lds_words(p->k, a.nb, p->s, a.rows_chunk);
+  const size_t lds = (size_t)16 * (reg ? reg_lds_words(a.nb, C) : bwd_lds_words(p->k, a.nb, p->s, a.rows_chunk));
   const int64_t groups = (int64_t)h * a.groups_x;
   if (groups > 0x7fffffff) return fail(GLU_ERR_UNSUPPORTED, "image too large");
   hipStream_t sm = (hipStream_t)stream;
-  BwdKernel kern = pick_bwd(T_low->dtype == GLU_F16, P, p->k, C);
+  BwdKernel kern = reg ? pick_reg(T_low->dtype == GLU_F16, C) : pick_bwd(T_low->dtype == GLU_F16, P, p->k, C);
   hipLaunchKernelGGL(kern, dim3((unsigned)groups, (unsigned)n), dim3(kThreads), lds, sm, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "backward pass 1 launch");

@@ -84,6 +84,15 @@ def _check(glu, H, W, s, k, C, seed, t_dtype=torch.float32):
         (7, 5, 8, 3, 1),
         (512, 512, 8, 3, 3),
         (96, 96, 32, 3, 3),
+        (72, 100, 4, 3, 4),
+        (70, 91, 8, 3, 3),
+        (40, 36, 12, 3, 3),
+        (200, 260, 64, 3, 3),
+        (300, 260, 128, 3, 1),
+        (33, 2100, 8, 3, 2),
+        (100, 130, 20, 3, 2),
+        (520, 300, 256, 3, 3),
+        (24, 20, 512, 3, 3),
     ],
 )
 def test_backward_parity(H, W, s, k, C):
