@@ -78,6 +78,17 @@ typedef enum { GLU_F32 = 0, GLU_F16 = 1 } glu_dtype;
  * of nearest colour, first in LR index on ties; E = that distance). */
 typedef enum { GLU_SEARCH_EXHAUSTIVE = 0, GLU_SEARCH_FAST = 1, GLU_SEARCH_GNU = 2 } glu_mode;
 
+/* glu_params.flags.  GLU_FLAG_NO_DEGENERATE (exhaustive mode only): the
+ * candidates are the unordered pairs i < j of the window alone (36 for 3 x 3,
+ * Sec. 3.2), without the single-cell candidates (i, i) with weight 1 that the
+ * default search adds; a window with a single cell (k = 1, or a 1 x 1 LR
+ * image) falls back to that cell.  With eps > 0 a pixel equal to a window
+ * colour then keeps a small error, since Eq. 4's weight never reaches 1.
+ * Taken by glu_search, glu_search_apply and batch plans; the joint
+ * downsampling calls return GLU_ERR_UNSUPPORTED for it, and the fast and GNU
+ * modes GLU_ERR_PARAM. */
+enum { GLU_FLAG_NO_DEGENERATE = 1u };
+
 /* Regular-grid downsampling keeps one HR pixel per LR pixel (Sec. 3.1,
  * Sec. 3.3); BOX averages the in-image pixels of each s x s block. */
 typedef enum { GLU_DOWN_POINT = 0, GLU_DOWN_BOX = 1 } glu_down_mode;
@@ -104,7 +115,7 @@ typedef struct {
   int32_t k;           /* odd window size, 1 <= k <= 15 (paper: 3)      */
   float eps;           /* Eq. 4 / Eq. 5 regulariser, >= 0 (paper: 1e-3) */
   glu_mode mode;
-  uint32_t flags;      /* reserved, must be 0                           */
+  uint32_t flags;      /* GLU_FLAG_* bits, 0 for the paper's search      */
 } glu_params;
 
 /* Per-round statistics of glu_joint_downsample (HOST struct). */

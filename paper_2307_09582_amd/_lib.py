@@ -26,6 +26,7 @@ STATUS_NAMES = {
 }
 GLU_F32, GLU_F16 = 0, 1
 GLU_SEARCH_EXHAUSTIVE, GLU_SEARCH_FAST, GLU_SEARCH_GNU = 0, 1, 2
+GLU_FLAG_NO_DEGENERATE = 1
 GLU_DOWN_POINT, GLU_DOWN_BOX = 0, 1
 
 

@@ -62,7 +62,9 @@ glu_status check_params(const glu_params* p) {
   if (!(p->eps >= 0.0f) || !std::isfinite(p->eps)) return fail(GLU_ERR_PARAM, "eps must be finite and >= 0");
   if (p->mode != GLU_SEARCH_EXHAUSTIVE && p->mode != GLU_SEARCH_FAST && p->mode != GLU_SEARCH_GNU)
     return fail(GLU_ERR_PARAM, "unknown mode %d", (int)p->mode);
-  if (p->flags != 0) return fail(GLU_ERR_PARAM, "flags must be 0");
+  if (p->flags & ~(uint32_t)GLU_FLAG_NO_DEGENERATE) return fail(GLU_ERR_PARAM, "unknown flags 0x%x", p->flags);
+  if ((p->flags & GLU_FLAG_NO_DEGENERATE) && p->mode != GLU_SEARCH_EXHAUSTIVE)
+    return fail(GLU_ERR_PARAM, "GLU_FLAG_NO_DEGENERATE applies to the exhaustive search only");
   return GLU_OK;
 }
 
@@ -283,6 +285,7 @@ static glu_status run_search(const glu_image* I, const glu_image* I_low, const g
   const TileChoice tc = choose_tile(p->s, p->k, mode, fused, table, tuned_variant(p->mode, p->k, p->s, I->dtype));
   fill_tiles(d, tc);
   d.gnu = p->mode == GLU_SEARCH_GNU;
+  d.no_degen = (p->flags & GLU_FLAG_NO_DEGENERATE) != 0;
   d.vec = launch_vec_flags(d, tc.P, dtype_size(I->dtype));
   const size_t lds = 16 * (size_t)search_tile_words(tc.tqy, tc.tqx, p->k, mode, fused, table);
   const int64_t ntiles = (int64_t)d.tiles_x * d.tiles_y;

@@ -196,6 +196,7 @@ static glu_status make_item(const glu_batch_item& it, const glu_params& p, int m
   const TileChoice tc = choose_tile(it.s, it.k, mode, true, table, var);
   fill_tiles(d, tc);
   d.gnu = p.mode == GLU_SEARCH_GNU;
+  d.no_degen = (p.flags & GLU_FLAG_NO_DEGENERATE) != 0;
   d.vec = launch_vec_flags(d, tc.P, dtype_size((glu_dtype)it.I.dtype));
   d.variant = kernel_variant(it.k, tc.P, mode, it.I.dtype);
   lds = 16 * (size_t)search_tile_words(tc.tqy, tc.tqx, it.k, mode, true, table);

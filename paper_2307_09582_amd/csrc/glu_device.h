@@ -251,9 +251,33 @@ struct GlobalWin {
 // most |I_p - L_j| (alpha >= 0 moves the point along the segment towards
 // the pixel), so only (0, 0) is evaluated.  Border windows evaluate every
 // valid candidate.
+// With the pairs i < j as the only candidates, a window with a single valid
+// cell (k = 1, or a 1 x 1 LR image) has none: its pixels take that cell
+// (code j k^2 + j, weight 1).  Pixels with a finite best are left alone.
+template <int P, typename Win>
+__device__ __forceinline__ void exh_lone_cell(const float (&ip)[P][3], const Win& win, int K2, float (&best)[P],
+                                              int (&code)[P]) {
+  bool any = false;
+#pragma unroll
+  for (int q = 0; q < P; ++q) any |= !(best[q] < __builtin_inff());
+  if (!any) return;
+  for (int j = 0; j < K2; ++j) {
+    const float4 Lj = win(j);
+    if (Lj.w == 0.0f) continue;
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+      if (best[q] < __builtin_inff()) continue;
+      const float dx = ip[q][0] - Lj.x, dy = ip[q][1] - Lj.y, dz = ip[q][2] - Lj.z;
+      best[q] = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+      code[q] = j * K2 + j;
+    }
+    break;
+  }
+}
+
 template <int KW, int P, bool BORDER, bool TABLE, typename Win>
 __device__ __forceinline__ void exh_strip(const float (&ip)[P][3], const Win& win,
-                                          const PairK* __restrict__ tab, float eps, int kw_rt,
+                                          const PairK* __restrict__ tab, float eps, int kw_rt, bool no_degen,
                                           float (&best)[P], int (&code)[P]) {
   constexpr int kUnrollJ = KW == 3 ? 9 : 1;
   constexpr int kUnrollI = KW == 3 ? 8 : 2;
@@ -264,7 +288,7 @@ __device__ __forceinline__ void exh_strip(const float (&ip)[P][3], const Win& wi
     best[q] = __builtin_inff();
     code[q] = 0;
   }
-  if (!BORDER) {
+  if (!BORDER && !no_degen) {
     const float4 L0 = win(0);
 #pragma unroll
     for (int q = 0; q < P; ++q) {
@@ -303,7 +327,7 @@ __device__ __forceinline__ void exh_strip(const float (&ip)[P][3], const Win& wi
         code[q] = lt ? cc : code[q];
       }
     }
-    if (BORDER) {
+    if (BORDER && !no_degen) {
       const int cc = j * K2 + j;
 #pragma unroll
       for (int q = 0; q < P; ++q) {
@@ -314,6 +338,7 @@ __device__ __forceinline__ void exh_strip(const float (&ip)[P][3], const Win& wi
       }
     }
   }
+  if (no_degen) exh_lone_cell<P>(ip, win, K2, best, code);
 }
 
 // Compile-time loop: f(std::integral_constant<int, I>) for I in [B, E).
@@ -339,15 +364,17 @@ constexpr int colex_i(int p) { return p - colex_j(p) * (colex_j(p) - 1) / 2; }
 // pair keeps only two records live (instead of all 36).
 template <int P, typename Win>
 __device__ __forceinline__ void exh_interior3(const float (&ip)[P][3], const Win& win,
-                                              const PairK* __restrict__ tab, float (&best)[P], int (&code)[P]) {
+                                              const PairK* __restrict__ tab, bool no_degen, float (&best)[P],
+                                              int (&code)[P]) {
   constexpr int K2 = 9;
   constexpr int NP = 36;
   {
+    // (0, 0) first, unless the pairs i < j are the only candidates
     const float4 L0 = win(0);
 #pragma unroll
     for (int q = 0; q < P; ++q) {
       const float dx = ip[q][0] - L0.x, dy = ip[q][1] - L0.y, dz = ip[q][2] - L0.z;
-      best[q] = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+      best[q] = no_degen ? __builtin_inff() : fmaf(dz, dz, fmaf(dy, dy, dx * dx));
       code[q] = 0;
     }
   }
@@ -726,13 +753,13 @@ __device__ __forceinline__ void search_tile(const ImgDesc& d, int ty, int tx, fl
     if (MODE == MODE_EXH) {
       if (interior) {
         if constexpr (KW == 3 && TABLE)
-          exh_interior3<P>(ip, win, tab, best, code);
+          exh_interior3<P>(ip, win, tab, d.no_degen != 0, best, code);
         else
-          exh_strip<KW, P, false, TABLE>(ip, win, tab, eps, kw, best, code);
+          exh_strip<KW, P, false, TABLE>(ip, win, tab, eps, kw, d.no_degen != 0, best, code);
 #pragma unroll
         for (int q = 0; q < P; ++q) al[q] = exh_alpha<KW, TABLE>(ip[q], win, tab, eps, kw, code[q]);
       } else {
-        exh_strip<KW, P, true, false>(ip, win, tab, eps, kw, best, code);
+        exh_strip<KW, P, true, false>(ip, win, tab, eps, kw, d.no_degen != 0, best, code);
 #pragma unroll
         for (int q = 0; q < P; ++q) al[q] = exh_alpha<KW, false>(ip[q], win, tab, eps, kw, code[q]);
       }

@@ -44,6 +44,7 @@ struct ImgDesc {
   int32_t dtype;        // glu_dtype of I, L, T, That
   int32_t variant;      // kernel variant index (batched dispatch)
   int32_t gnu;          // fast-mode kernels: stop after the anchor (GNU)
+  int32_t no_degen;     // exhaustive: pairs i < j only (GLU_FLAG_NO_DEGENERATE)
   int64_t tile_begin;   // first global tile index of this image (batched)
 };
 

@@ -177,6 +177,7 @@ glu_status glu_joint_downsample_grad(const glu_image* I, glu_image* I_low, const
   clear_error();
   glu_status st;
   if ((st = check_params(p))) return st;
+  if (p->flags) return fail(GLU_ERR_UNSUPPORTED, "joint downsampling takes no flags");
   if ((st = check_image(I, "I", 3, 3, false))) return st;
   if ((st = check_image(I_low, "I_low", 3, 3, false))) return st;
   const int H = I->height, W = I->width;

@@ -255,7 +255,7 @@ __device__ __forceinline__ void search_one(const JdTrialArgs& a, int y, int x, i
   float best[1], alp[1];
   int cd[1];
   if (a.mode == MODE_EXH) {
-    exh_strip<0, 1, true, false>(ip, win, nullptr, a.eps, a.k, best, cd);
+    exh_strip<0, 1, true, false>(ip, win, nullptr, a.eps, a.k, false, best, cd);
     alp[0] = exh_alpha<0, false>(ip[0], win, nullptr, a.eps, a.k, cd[0]);
   } else {
     fast_strip<0, 1, true>(ip, win, a.eps, a.k, a.gnu != 0, best, cd, alp);
@@ -463,6 +463,7 @@ glu_status glu_joint_downsample(const glu_image* I, glu_image* I_low, const glu_
   clear_error();
   glu_status st;
   if ((st = check_params(p))) return st;
+  if (p->flags) return fail(GLU_ERR_UNSUPPORTED, "joint downsampling takes no flags");
   if ((st = check_image(I, "I", 3, 3, false))) return st;
   if ((st = check_image(I_low, "I_low", 3, 3, false))) return st;
   if (!(tau >= 0.0f) || !std::isfinite(tau)) return fail(GLU_ERR_PARAM, "tau must be finite and >= 0");

@@ -71,10 +71,11 @@ def _theta(th: Theta) -> L.glu_theta:
     )
 
 
-def _params(s: int, k: int, eps: float, mode: str = "exhaustive") -> L.glu_params:
+def _params(s: int, k: int, eps: float, mode: str = "exhaustive", degenerate: bool = True) -> L.glu_params:
     if mode not in _MODES:
         raise ValueError("mode must be 'exhaustive', 'fast' or 'gnu'")
-    return L.glu_params(int(s), int(k), float(eps), _MODES[mode], 0)
+    flags = 0 if degenerate else L.GLU_FLAG_NO_DEGENERATE
+    return L.glu_params(int(s), int(k), float(eps), _MODES[mode], flags)
 
 
 def lr_shape(H: int, W: int, s: int):
@@ -97,13 +98,16 @@ def downsample(I: torch.Tensor, s: int, mode: str = "point") -> torch.Tensor:
     return out
 
 
-def search(I, I_low, s, k=3, eps=EPS, mode="exhaustive", return_err=False, theta: Theta | None = None, err=None):
-    """Per-pixel (a, b, alpha) search; returns Theta (and E when return_err)."""
+def search(I, I_low, s, k=3, eps=EPS, mode="exhaustive", return_err=False, theta: Theta | None = None, err=None,
+           degenerate=True):
+    """Per-pixel (a, b, alpha) search; returns Theta (and E when return_err).
+    degenerate=False (exhaustive only) keeps the pairs i < j alone as
+    candidates (GLU_FLAG_NO_DEGENERATE)."""
     H, W = I.shape[:2]
     theta = theta if theta is not None else empty_theta(H, W, I.device)
     if return_err and err is None:
         err = torch.empty((H, W), dtype=torch.float32, device=I.device)
-    p = _params(s, k, eps, mode)
+    p = _params(s, k, eps, mode, degenerate)
     lib = L.load()
     L.check(
         lib.glu_search(
@@ -174,7 +178,7 @@ def _apply_batched(theta: Theta, T_low, s, k, out):
 
 def search_apply(
     I, I_low, T_low, s, k=3, eps=EPS, mode="exhaustive", store_theta=True, return_err=False, theta=None, out=None,
-    err=None,
+    err=None, degenerate=True,
 ):
     """Fused search + apply; returns (T_hat, Theta or None[, E])."""
     H, W = I.shape[:2]
@@ -184,7 +188,7 @@ def search_apply(
         out = torch.empty((H, W, T_low.shape[2]), dtype=T_low.dtype, device=I.device)
     if return_err and err is None:
         err = torch.empty((H, W), dtype=torch.float32, device=I.device)
-    p = _params(s, k, eps, mode)
+    p = _params(s, k, eps, mode, degenerate)
     lib = L.load()
     th = C.byref(_theta(theta)) if theta is not None else None
     L.check(
@@ -441,10 +445,10 @@ class BatchPlan:
     optional Theta.  The tensors must stay alive while the plan is used.
     """
 
-    def __init__(self, items, eps=EPS, mode="exhaustive"):
+    def __init__(self, items, eps=EPS, mode="exhaustive", degenerate=True):
         self.items = list(items)
         arr = (L.glu_batch_item * max(1, len(self.items)))(*[_batch_item(it) for it in self.items])
-        p = _params(1, 3, eps, mode)
+        p = _params(1, 3, eps, mode, degenerate)
         lib = L.load()
         h = C.c_void_p()
         L.check(lib.glu_batch_plan_create(arr, len(self.items), C.byref(p), C.byref(h)))

@@ -59,7 +59,7 @@ class ParityReport(dict):
 
 
 def check_search(I, L, s, k, eps, mode, code, alpha, err=None, pixels=None, T_low=None, T_hat=None,
-                 out_dtype=np.float32):
+                 out_dtype=np.float32, degenerate=True):
     """Runs the oracle on `pixels` (default all) and checks the GPU outputs.
 
     I, L, T_low: host arrays of the exact values the GPU consumed.
@@ -79,7 +79,11 @@ def check_search(I, L, s, k, eps, mode, code, alpha, err=None, pixels=None, T_lo
     assert ok.all(), "GPU codes point outside the LR image at %d pixels" % int((~ok).sum())
     assert _in_window(a_g, pixels, W, s, k, h, w).all() and _in_window(b_g, pixels, W, s, k, h, w).all()
     al_g = np.asarray(alpha, dtype=np.float64).reshape(-1)[pixels]
-    ref = O.search(I, L, s, k, eps, mode, pixels=pixels)
+    if degenerate:
+        ref = O.search(I, L, s, k, eps, mode, pixels=pixels)
+    else:
+        assert mode == "exhaustive", "the pairs-only candidate set is an exhaustive-search option"
+        ref = O.search_exhaustive(I, L, s, k, eps, pixels=pixels, degenerate=False)
     if mode == "gnu":
         # the anchor alone: a near-tie of the nearest colour, b = a, weight 1
         Lf = np.asarray(L, dtype=np.float64).reshape(-1, 3)

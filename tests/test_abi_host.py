@@ -70,7 +70,9 @@ def _search(I, Il, p, th):
         (dict(p=_params(eps=-1.0)), 4),
         (dict(p=_params(eps=float("nan"))), 4),
         (dict(p=_params(mode=7)), 4),
-        (dict(p=_params(flags=1)), 4),
+        (dict(p=_params(flags=2)), 4),
+        (dict(p=_params(mode=1, flags=1)), 4),
+        (dict(p=_params(mode=2, flags=1)), 4),
         (dict(I=_img(Cn=4)), 2),
         (dict(Il=_img(H=3, W=2)), 2),
         (dict(Il=_img(H=2, W=2, dt=L.GLU_F16)), 3),
@@ -176,3 +178,21 @@ def test_joint_downsample_grad_validation():
     st = lib.glu_joint_downsample_grad(C.byref(I), C.byref(Il), C.byref(p), 0.01, 2, 1, C.byref(th2), None,
                                        0x100000, ws, None, None, None)
     assert st == 2
+
+
+def test_joint_downsampling_rejects_flags():
+    """The pairs-only candidate set (GLU_FLAG_NO_DEGENERATE) is a search
+    option: both joint downsampling calls refuse it before any HIP call."""
+    lib = L.load()
+    p = _params(s=4, flags=L.GLU_FLAG_NO_DEGENERATE)
+    I = _img(H=8, W=8)
+    Il = _img(ptr=0x4000, H=2, W=2)
+    th = _theta()
+    ws = lib.glu_joint_downsample_grad_workspace(8, 8, C.byref(p))
+    st = lib.glu_joint_downsample_grad(C.byref(I), C.byref(Il), C.byref(p), 0.01, 2, 1, C.byref(th), 0x7000,
+                                       0x100000, ws, None, None, None)
+    assert st == 8 and b"flags" in lib.glu_last_error()
+    wsj = lib.glu_joint_downsample_workspace(8, 8, C.byref(p))
+    st = lib.glu_joint_downsample(C.byref(I), C.byref(Il), C.byref(p), 30.0 / 255, 3, C.byref(th), 0x7000,
+                                  0x100000, wsj, None, None, None)
+    assert st == 8 and b"flags" in lib.glu_last_error()

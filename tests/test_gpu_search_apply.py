@@ -297,6 +297,41 @@ def test_apply_random_theta(H, W, s, k, C, dt, pad, off):
         assert np.isnan(rest[:, off + W:]).all()
 
 
+@pytest.mark.parametrize("H,W,s,k,C", [(64, 80, 4, 3, 3), (37, 53, 5, 5, 1), (9, 7, 16, 3, 3), (40, 40, 4, 1, 3),
+                                        (130, 170, 8, 3, 2)])
+def test_no_degenerate_flag(H, W, s, k, C):
+    """GLU_FLAG_NO_DEGENERATE: the pairs i < j alone, against the oracle's
+    literal candidate set, through search, the fused pass and a batch plan;
+    on noise-free inputs, where the flag changes the result."""
+    glu = _glu()
+    log_case(test="no_degenerate", H=H, W=W, s=s, k=k, C=C)
+    I = synth.voronoi(H, W, n_cells=max(4, H * W // 300), n_dots=2, dot_px=(1, 3), sigma=0.0, seed=H * 3 + W)
+    L = np.ascontiguousarray(O.downsample_point(I, s).astype(np.float32))
+    T = np.ascontiguousarray(synth.lr_op_f1(L)[..., :C].astype(np.float32))
+    dI, dL, dT = dev(I.astype(np.float32)), dev(L), dev(T)
+    th, err = glu.search(dI, dL, s, k, 1e-3, "exhaustive", return_err=True, degenerate=False)
+    out = glu.apply(th, dT, s, k)
+    code, alpha, e = host(th.code), host(th.alpha), host(err)
+    check_search(I.astype(np.float32), L, s, k, 1e-3, "exhaustive", code, alpha, err=e, T_low=T, T_hat=host(out),
+                 degenerate=False)
+    out2, th2, err2 = glu.search_apply(dI, dL, dT, s, k, 1e-3, "exhaustive", return_err=True, degenerate=False)
+    assert np.array_equal(host(th2.code), code) and np.array_equal(host(out2), host(out))
+    it = dict(I=dI, I_low=dL, T_low=dT, s=s, k=k, T_hat=torch.empty((H, W, C), dtype=torch.float32, device="cuda"))
+    plan = glu.BatchPlan([it], mode="exhaustive", degenerate=False)
+    plan.launch()
+    assert torch.equal(it["T_hat"], out2)
+    plan.close()
+    # the default candidate set reaches zero error where a pixel equals a
+    # window colour; the pairs alone leave a residual there (unless k = 1 or
+    # a single LR cell, where both take the lone cell)
+    _, err_d = glu.search(dI, dL, s, k, 1e-3, "exhaustive", return_err=True)
+    e_d = host(err_d)
+    if k > 1 and L.shape[0] * L.shape[1] > 1:
+        assert ((e_d == 0) & (e > 0)).any()
+    else:
+        assert np.array_equal(e, e_d)
+
+
 @pytest.mark.parametrize("H,W,s,k,C,dt", [(200, 264, 8, 3, 3, "f32"), (37, 53, 4, 5, 1, "f32"), (29, 31, 3, 3, 3, "f16"),
                                            (41, 39, 4, 7, 2, "f32")])
 def test_gnu_mode(H, W, s, k, C, dt):
