@@ -617,30 +617,27 @@ __host__ __device__ inline int search_tile_words(int tqy, int tqx, int k, int mo
   return words;
 }
 
+// One LR cell of a tile's staging: the guide (with the inside-image flag in
+// .w) and, when sT is wanted, the target; zeros outside the image.
 template <typename T>
-__device__ __forceinline__ void stage_lr(const ImgDesc& d, int qy0, int qx0, int R, int ly, int lx,
-                                         float4* sL, float4* sT) {
+__device__ __forceinline__ void load_lr_cell(const ImgDesc& d, int qy0, int qx0, int R, int lx, int c, bool want_t,
+                                             float4& v, float4& tv) {
   const T* __restrict__ L = static_cast<const T*>(d.L);
   const T* __restrict__ TL = static_cast<const T*>(d.T);
-  const int ncell = ly * lx;
-  for (int c = threadIdx.x; c < ncell; c += kThreads) {
-    const int oy = c / lx;
-    const int cy = qy0 - R + oy, cx = qx0 - R + (c - oy * lx);
-    float4 v = make_float4(0.f, 0.f, 0.f, 0.f), tv = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (cy >= 0 && cy < d.h && cx >= 0 && cx < d.w) {
-      if (sL) {
-        const T* q = L + (int64_t)cy * d.L_stride + (int64_t)cx * 3;
-        v = make_float4(to_f<T>(q[0]), to_f<T>(q[1]), to_f<T>(q[2]), 1.0f);
-      }
-      if (sT) {
-        const T* q = TL + (int64_t)cy * d.T_stride + (int64_t)cx * d.C;
-        float tt[4] = {0.f, 0.f, 0.f, 0.f};
-        for (int ch = 0; ch < d.C; ++ch) tt[ch] = to_f<T>(q[ch]);
-        tv = make_float4(tt[0], tt[1], tt[2], tt[3]);
-      }
+  const int oy = c / lx;
+  const int cy = qy0 - R + oy, cx = qx0 - R + (c - oy * lx);
+  v = make_float4(0.f, 0.f, 0.f, 0.f);
+  tv = v;
+  if (cy >= 0 && cy < d.h && cx >= 0 && cx < d.w) {
+    const T* q = L + (int64_t)cy * d.L_stride + (int64_t)cx * 3;
+    v = make_float4(to_f<T>(q[0]), to_f<T>(q[1]), to_f<T>(q[2]), 1.0f);
+    if (want_t) {
+      const T* t = TL + (int64_t)cy * d.T_stride + (int64_t)cx * d.C;
+      float tt[4];
+#pragma unroll
+      for (int ch = 0; ch < 4; ++ch) tt[ch] = ch < d.C ? to_f<T>(t[ch]) : 0.f;
+      tv = make_float4(tt[0], tt[1], tt[2], tt[3]);
     }
-    if (sL) sL[c] = v;
-    if (sT) sT[c] = tv;
   }
 }
 
@@ -687,9 +684,23 @@ __device__ __forceinline__ void search_tile(const ImgDesc& d, int ty, int tx, fl
     if (y >= d.H || x >= d.W) return;
     load_strip3<T, P>(Ig + (int64_t)y * d.I_stride, x, d.W, vecI, interior || (x + P <= d.W), ipn);
   };
+  // The tile's first round of LR cells is loaded into registers, then the
+  // first strip's pixels, and only then are the cells written to LDS: the
+  // two sets of loads are in flight together (a staging loop ahead of the
+  // prefetch would wait for it at its head).
+  float4 lv, ltv;
+  const bool lr_first = (int)threadIdx.x < ncell;
+  if (lr_first) load_lr_cell<T>(d, qy0, qx0, R, lx, threadIdx.x, FUSED, lv, ltv);
   prefetch(threadIdx.x);
-
-  stage_lr<T>(d, qy0, qx0, R, ly, lx, sL, sT);
+  if (lr_first) {
+    sL[threadIdx.x] = lv;
+    if (FUSED) sT[threadIdx.x] = ltv;
+  }
+  for (int c = threadIdx.x + kThreads; c < ncell; c += kThreads) {
+    load_lr_cell<T>(d, qy0, qx0, R, lx, c, FUSED, lv, ltv);
+    sL[c] = lv;
+    if (FUSED) sT[c] = ltv;
+  }
   if constexpr (kOffTab) {
     for (int c = threadIdx.x; c < K2 * K2; c += kThreads) {
       const int oa = c / K2, ob = c - oa * K2;
