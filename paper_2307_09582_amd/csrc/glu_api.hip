@@ -123,19 +123,19 @@ void fill_tiles(ImgDesc& d, const TileChoice& tc) {
 
 static int kw_class(int k) { return k == 3 ? 0 : (k == 5 ? 1 : 2); }
 
-int kernel_variant(int k, int P, int mode, int dtype) {
-  return ((kw_class(k) * 2 + (P == 4 ? 0 : 1)) * 2 + mode) * 2 + dtype;
+int kernel_variant(int k, int P, int mode, int dtype, bool table) {
+  return (((kw_class(k) * 2 + (P == 4 ? 0 : 1)) * 2 + mode) * 2 + dtype) * 2 + (table ? 1 : 0);
 }
 
 // ---------------------------------------------------------------------------
 // kernels
 // ---------------------------------------------------------------------------
-template <int KW, int P, int MODE, typename T, bool FUSED>
+template <int KW, int P, int MODE, typename T, bool FUSED, bool TABLE>
 __global__ __launch_bounds__(kThreads) void k_search(const ImgDesc d, float eps) {
   extern __shared__ float4 smem[];
   const int tile = blockIdx.x;
   const int ty = tile / d.tiles_x, tx = tile - ty * d.tiles_x;
-  search_tile<KW, P, MODE, T, FUSED, uses_pair_table(MODE, KW)>(d, ty, tx, eps, smem);
+  search_tile<KW, P, MODE, T, FUSED, TABLE>(d, ty, tx, eps, smem);
 }
 
 // One workgroup per tile of one LR row by d.tqx LR columns; blockIdx.y is
@@ -167,26 +167,32 @@ typedef void (*SearchKernel)(const ImgDesc, float);
 typedef void (*ApplyKernel)(const ImgDesc, uint32_t, const ApplyBatch);
 
 template <int KW, int P, typename T>
-static SearchKernel pick_search_t(int mode, bool fused) {
-  if (mode == MODE_EXH)
-    return fused ? k_search<KW, P, MODE_EXH, T, true> : k_search<KW, P, MODE_EXH, T, false>;
-  return fused ? k_search<KW, P, MODE_FAST, T, true> : k_search<KW, P, MODE_FAST, T, false>;
+static SearchKernel pick_search_t(int mode, bool fused, bool table) {
+  if (mode == MODE_EXH) {
+    if constexpr (kernel_has_table(MODE_EXH, KW)) {
+      if (table)
+        return fused ? k_search<KW, P, MODE_EXH, T, true, true> : k_search<KW, P, MODE_EXH, T, false, true>;
+    }
+    return fused ? k_search<KW, P, MODE_EXH, T, true, false> : k_search<KW, P, MODE_EXH, T, false, false>;
+  }
+  return fused ? k_search<KW, P, MODE_FAST, T, true, false> : k_search<KW, P, MODE_FAST, T, false, false>;
 }
 
 template <int KW, int P>
-static SearchKernel pick_search_p(int mode, int dtype, bool fused) {
-  return dtype == GLU_F16 ? pick_search_t<KW, P, __half>(mode, fused) : pick_search_t<KW, P, float>(mode, fused);
+static SearchKernel pick_search_p(int mode, int dtype, bool fused, bool table) {
+  return dtype == GLU_F16 ? pick_search_t<KW, P, __half>(mode, fused, table)
+                          : pick_search_t<KW, P, float>(mode, fused, table);
 }
 
 template <int KW>
-static SearchKernel pick_search_k(int P, int mode, int dtype, bool fused) {
-  return P == 4 ? pick_search_p<KW, 4>(mode, dtype, fused) : pick_search_p<KW, 1>(mode, dtype, fused);
+static SearchKernel pick_search_k(int P, int mode, int dtype, bool fused, bool table) {
+  return P == 4 ? pick_search_p<KW, 4>(mode, dtype, fused, table) : pick_search_p<KW, 1>(mode, dtype, fused, table);
 }
 
-static SearchKernel pick_search(int k, int P, int mode, int dtype, bool fused) {
-  if (k == 3) return pick_search_k<3>(P, mode, dtype, fused);
-  if (k == 5) return pick_search_k<5>(P, mode, dtype, fused);
-  return pick_search_k<0>(P, mode, dtype, fused);
+static SearchKernel pick_search(int k, int P, int mode, int dtype, bool fused, bool table) {
+  if (k == 3) return pick_search_k<3>(P, mode, dtype, fused, table);
+  if (k == 5) return pick_search_k<5>(P, mode, dtype, fused, table);
+  return pick_search_k<0>(P, mode, dtype, fused, table);
 }
 
 template <int KW>
@@ -281,7 +287,7 @@ static glu_status run_search(const glu_image* I, const glu_image* I_low, const g
   d.C = C;
   d.dtype = I->dtype;
   const int mode = p->mode == GLU_SEARCH_EXHAUSTIVE ? MODE_EXH : MODE_FAST;
-  const bool table = uses_pair_table(mode, p->k);
+  const bool table = uses_pair_table(mode, p->k, p->s);
   const TileChoice tc = choose_tile(p->s, p->k, mode, fused, table, tuned_variant(p->mode, p->k, p->s, I->dtype));
   fill_tiles(d, tc);
   d.gnu = p->mode == GLU_SEARCH_GNU;
@@ -290,7 +296,7 @@ static glu_status run_search(const glu_image* I, const glu_image* I_low, const g
   const size_t lds = 16 * (size_t)search_tile_words(tc.tqy, tc.tqx, p->k, mode, fused, table);
   const int64_t ntiles = (int64_t)d.tiles_x * d.tiles_y;
   if (ntiles > 0x7fffffff) return fail(GLU_ERR_UNSUPPORTED, "image needs too many tiles");
-  SearchKernel kern = pick_search(p->k, tc.P, mode, I->dtype, fused);
+  SearchKernel kern = pick_search(p->k, tc.P, mode, I->dtype, fused, table);
   hipLaunchKernelGGL(kern, dim3((unsigned)ntiles), dim3(kThreads), lds, (hipStream_t)stream, d, p->eps);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "search launch");

@@ -72,7 +72,7 @@ __device__ __forceinline__ int64_t uniform_i64(int64_t v) {
   return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
-template <int MODE, int KW, int P, typename T>
+template <int MODE, int KW, int P, typename T, bool TABLE>
 __global__ __launch_bounds__(kThreads) void k_batch(const BatchTable tab) {
   extern __shared__ float4 smem[];
   {
@@ -99,27 +99,35 @@ __global__ __launch_bounds__(kThreads) void k_batch(const BatchTable tab) {
     }
     const int64_t local = t - d.tile_begin;
     const int ty = (int)(local / d.tiles_x), tx = (int)(local - (int64_t)ty * d.tiles_x);
-    search_tile<KW, P, MODE, T, true, uses_pair_table(MODE, KW)>(d, ty, tx, tab.eps, smem);
+    search_tile<KW, P, MODE, T, true, TABLE>(d, ty, tx, tab.eps, smem);
   }
 }
 
 typedef void (*BatchKernel)(const BatchTable);
 
+template <int MODE, int KW, bool TABLE>
+static BatchKernel pick_batch_kwt(int P, int dtype) {
+  if (P == 4) return dtype == GLU_F16 ? k_batch<MODE, KW, 4, __half, TABLE> : k_batch<MODE, KW, 4, float, TABLE>;
+  return dtype == GLU_F16 ? k_batch<MODE, KW, 1, __half, TABLE> : k_batch<MODE, KW, 1, float, TABLE>;
+}
+
 template <int MODE, int KW>
-static BatchKernel pick_batch_kw(int P, int dtype) {
-  if (P == 4) return dtype == GLU_F16 ? k_batch<MODE, KW, 4, __half> : k_batch<MODE, KW, 4, float>;
-  return dtype == GLU_F16 ? k_batch<MODE, KW, 1, __half> : k_batch<MODE, KW, 1, float>;
+static BatchKernel pick_batch_kw(int P, int dtype, bool table) {
+  if constexpr (kernel_has_table(MODE, KW)) {
+    if (table) return pick_batch_kwt<MODE, KW, true>(P, dtype);
+  }
+  return pick_batch_kwt<MODE, KW, false>(P, dtype);
 }
 
 template <int MODE>
-static BatchKernel pick_batch_m(int k, int P, int dtype) {
-  if (k == 3) return pick_batch_kw<MODE, 3>(P, dtype);
-  if (k == 5) return pick_batch_kw<MODE, 5>(P, dtype);
-  return pick_batch_kw<MODE, 0>(P, dtype);
+static BatchKernel pick_batch_m(int k, int P, int dtype, bool table) {
+  if (k == 3) return pick_batch_kw<MODE, 3>(P, dtype, table);
+  if (k == 5) return pick_batch_kw<MODE, 5>(P, dtype, table);
+  return pick_batch_kw<MODE, 0>(P, dtype, table);
 }
 
-static BatchKernel pick_batch(int mode, int k, int P, int dtype) {
-  return mode == MODE_EXH ? pick_batch_m<MODE_EXH>(k, P, dtype) : pick_batch_m<MODE_FAST>(k, P, dtype);
+static BatchKernel pick_batch(int mode, int k, int P, int dtype, bool table) {
+  return mode == MODE_EXH ? pick_batch_m<MODE_EXH>(k, P, dtype, table) : pick_batch_m<MODE_FAST>(k, P, dtype, table);
 }
 
 // One launch of a plan: the images of one kernel variant.
@@ -191,14 +199,14 @@ static glu_status make_item(const glu_batch_item& it, const glu_params& p, int m
   d.k = it.k;
   d.C = it.T_low.channels;
   d.dtype = it.I.dtype;
-  const bool table = uses_pair_table(mode, it.k);
+  const bool table = uses_pair_table(mode, it.k, it.s);
   const int var = variant_override >= 0 ? variant_override : tuned_variant(p.mode, it.k, it.s, it.I.dtype);
   const TileChoice tc = choose_tile(it.s, it.k, mode, true, table, var);
   fill_tiles(d, tc);
   d.gnu = p.mode == GLU_SEARCH_GNU;
   d.no_degen = (p.flags & GLU_FLAG_NO_DEGENERATE) != 0;
   d.vec = launch_vec_flags(d, tc.P, dtype_size((glu_dtype)it.I.dtype));
-  d.variant = kernel_variant(it.k, tc.P, mode, it.I.dtype);
+  d.variant = kernel_variant(it.k, tc.P, mode, it.I.dtype, table);
   lds = 16 * (size_t)search_tile_words(tc.tqy, tc.tqx, it.k, mode, true, table);
   return GLU_OK;
 }
@@ -241,7 +249,7 @@ static glu_status plan_build(const glu_batch_item* items, int32_t n, const glu_p
     ImgDesc d = all[order[j]];
     if (groups.empty() || host.back().variant != d.variant) {
       BatchGroup g{};
-      g.kern = pick_batch(mode, d.k, (d.s % 4 == 0) ? 4 : 1, d.dtype);
+      g.kern = pick_batch(mode, d.k, (d.s % 4 == 0) ? 4 : 1, d.dtype, uses_pair_table(mode, d.k, d.s));
       g.first = (int32_t)host.size();
       g.lds = 16;
       groups.push_back(g);

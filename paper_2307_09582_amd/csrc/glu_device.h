@@ -594,10 +594,18 @@ __device__ __forceinline__ void store_staged(float4* buf, int lane, int C, int o
 enum { MODE_EXH = 0, MODE_FAST = 1 };
 
 // The exhaustive search reads per-cell pair constants from an LDS table for
-// 3 x 3 windows (36 pairs, 1152 bytes per LR cell).  Larger windows (300
-// pairs for 5 x 5) would shrink the tiles below one strip per thread, so
-// they build the constants of each pair once per strip instead.
-__host__ __device__ constexpr bool uses_pair_table(int mode, int k) { return mode == MODE_EXH && k == 3; }
+// 3 x 3 windows (36 pairs, 1184 bytes per LR cell), shared by the s^2 pixels
+// of the cell.  Larger windows (300 pairs for 5 x 5) would shrink the tiles
+// below one strip per thread, so they build the constants of each pair once
+// per strip instead; so do 3 x 3 windows with s < 5, whose cells are too
+// small to pay for their table (the tile that fits the LDS budget then
+// leaves threads idle).  Both forms use pair_consts, so they give bitwise
+// the same results.
+constexpr int kMinTableS = 5;
+__host__ __device__ constexpr bool kernel_has_table(int mode, int k) { return mode == MODE_EXH && k == 3; }
+__host__ __device__ constexpr bool uses_pair_table(int mode, int k, int s) {
+  return kernel_has_table(mode, k) && s >= kMinTableS;
+}
 
 // Output staging of the fused search: per wave, 64 strips of 4 pixels of 3
 // float channels (48 bytes each).

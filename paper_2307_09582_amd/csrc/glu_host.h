@@ -47,7 +47,7 @@ int n_tile_variants();
 void fill_tiles(ImgDesc& d, const TileChoice& tc);
 
 // Kernel variant index used by the batched dispatcher.
-int kernel_variant(int k, int P, int mode, int dtype);
+int kernel_variant(int k, int P, int mode, int dtype, bool table);
 
 // VEC_* alignment flags of a launch (vector loads / stores allowed).
 uint32_t launch_vec_flags(const ImgDesc& d, int P, size_t esize);
