@@ -472,7 +472,7 @@ def _configs(np, torch, synth, glu, dev, stream, scene):
                             lambda i: glu.search_apply(I, Il8, T8, 8, kk, EPS, mode, theta=thw, out=ow), n, 3)
             row[mode] = {"us": round(1e3 * ms, 1), "Mpx_s": round(H * W / (ms * 1e-3) / 1e6, 1)}
         sweep["k_at_s8"][str(kk)] = row
-    for ss in (4, 8, 16, 32, 64, 128):
+    for ss in (2, 3, 4, 6, 8, 16, 32, 64, 128):
         Ils = glu.downsample(I, ss, "point")
         Ts = _lr_f1_torch(torch, Ils).contiguous()
         row = {}

@@ -108,6 +108,8 @@ typedef void (*BatchKernel)(const BatchTable);
 template <int MODE, int KW, bool TABLE>
 static BatchKernel pick_batch_kwt(int P, int dtype) {
   if (P == 4) return dtype == GLU_F16 ? k_batch<MODE, KW, 4, __half, TABLE> : k_batch<MODE, KW, 4, float, TABLE>;
+  if (P == 3) return dtype == GLU_F16 ? k_batch<MODE, KW, 3, __half, TABLE> : k_batch<MODE, KW, 3, float, TABLE>;
+  if (P == 2) return dtype == GLU_F16 ? k_batch<MODE, KW, 2, __half, TABLE> : k_batch<MODE, KW, 2, float, TABLE>;
   return dtype == GLU_F16 ? k_batch<MODE, KW, 1, __half, TABLE> : k_batch<MODE, KW, 1, float, TABLE>;
 }
 
@@ -249,7 +251,7 @@ static glu_status plan_build(const glu_batch_item* items, int32_t n, const glu_p
     ImgDesc d = all[order[j]];
     if (groups.empty() || host.back().variant != d.variant) {
       BatchGroup g{};
-      g.kern = pick_batch(mode, d.k, (d.s % 4 == 0) ? 4 : 1, d.dtype, uses_pair_table(mode, d.k, d.s));
+      g.kern = pick_batch(mode, d.k, strip_pixels(d.s), d.dtype, uses_pair_table(mode, d.k, d.s));
       g.first = (int32_t)host.size();
       g.lds = 16;
       groups.push_back(g);

@@ -37,6 +37,10 @@ struct TileChoice {
   int tqx;  // tile width in LR centres
 };
 
+// Pixels per search strip: consecutive pixels of one HR row that share a
+// centre, so P divides s (4, else 3, else 2, else 1).
+inline int strip_pixels(int s) { return s % 4 == 0 ? 4 : (s % 3 == 0 ? 3 : (s % 2 == 0 ? 2 : 1)); }
+
 // Default tile: about 64 HR columns by enough rows for 256 strips, shrunk
 // until the LDS of the tile fits.  `variant` selects alternatives for the
 // autotuner (0 = default).

@@ -41,6 +41,8 @@ SPECS = [
     (33, 250, 2, 3, 3, "f16"),
     (1, 1, 1, 3, 1, "f32"),
     (260, 300, 4, 3, 3, "f32"),
+    (90, 110, 6, 3, 3, "f32"),
+    (52, 70, 10, 5, 2, "f16"),
 ]
 
 

@@ -102,6 +102,14 @@ CASES = [
     (300, 400, 64, 3, 3, "exhaustive", "f32"),
     (260, 520, 128, 3, 3, "fast", "f32"),
     (200, 200, 64, 5, 1, "fast", "f32"),
+    (61, 75, 6, 3, 3, "exhaustive", "f32"),
+    (61, 75, 6, 3, 3, "fast", "f32"),
+    (44, 58, 10, 3, 2, "exhaustive", "f16"),
+    (70, 90, 6, 5, 3, "exhaustive", "f32"),
+    (37, 41, 2, 3, 4, "exhaustive", "f32"),
+    (80, 100, 9, 3, 3, "exhaustive", "f32"),
+    (80, 100, 9, 3, 3, "fast", "f16"),
+    (33, 47, 3, 5, 3, "exhaustive", "f32"),
 ]
 
 
