@@ -13,10 +13,11 @@
 //     block of the part of their contribution aimed at the cell
 //     c + offset(o).  dL/dalpha is computed from LR target cells staged in
 //     LDS and written on the way.  Two forms, both with fixed orders:
-//     * registers (3 x 3 windows, s a multiple of 4 up to 256): a lane
-//       owns a 4-pixel column of a cell's block and every fourth HR row of
-//       it, and keeps 9 C sums (window offset, channel) in registers; the
-//       lanes of a cell, then the four waves, add theirs in a fixed order.
+//     * registers (3 x 3 windows, s with a strip width of 4, 3 or 2
+//       pixels): a lane owns a column of P pixels of a cell's block and
+//       every RW-th HR row of it, and keeps 9 C sums (window offset,
+//       channel) in registers; the lanes of a cell, then the row groups,
+//       add theirs in a fixed order.
 //     * scan (every other shape): a workgroup owns nb consecutive cells of
 //       one LR row (nb * k^2 <= 256), streams chunks of its HR rows into
 //       LDS, and one lane per (cell, offset) scans the chunk's pixels of
@@ -327,29 +328,49 @@ static BwdKernel pick_bwd(bool f16, int P, int k, int C) {
   return P == 4 ? pick_bwd_k<float, 4>(k, C) : pick_bwd_k<float, 1>(k, C);
 }
 
-// Register form of pass 1 (k = 3, s = 4 cps <= 256).  A workgroup owns
-// nb = floor(256 / s) cells of LR row qy, a segment of nb s pixels of its s
-// HR rows.  Wave v takes the rows y0 + v + 4 i; lane l < nb cps the pixels
-// x0 + 4 l .. + 3 of them, all in cell l / cps.  Each lane keeps 9 C sums
-// in registers, one per window offset and channel: a pixel adds alpha G
-// where o_a = o and (1 - alpha) G where o_b = o.  The first lane of a cell
-// adds up the sums of its cps lanes (cross-lane reads in a fixed order),
-// the four waves' sums meet in LDS, and one lane per (offset, cell) adds
-// them in wave order and writes S.
+// Register form of pass 1 (k = 3; strips of P = 4, 3 or 2 pixels, P the
+// largest of them that divides s; cps = s / P lanes per cell row, at most
+// 64).  The four waves of a workgroup form RW = min(4, s) row groups times
+// SG = 4 / RW column segments (for s = 3 the fourth wave idles).  A
+// segment holds nbs = floor(64 / cps) cells of LR row qy, and the
+// workgroup nb = SG nbs of them.  Wave v takes segment v / RW and the HR
+// rows y0 + (v mod RW) + RW i; lane l the pixels P l .. P l + P - 1 of the
+// segment, all in the segment's cell l / cps.  Each lane keeps 9 C sums in
+// registers, one per window offset and channel: a pixel adds alpha G where
+// o_a = o and (1 - alpha) G where o_b = o.  The first lane of a cell adds
+// up the sums of its cps lanes (cross-lane reads in a fixed order), the
+// row groups' sums meet in LDS, and one lane per (offset, cell) adds them in
+// row-group order and writes S.
 constexpr int kRegWaves = kThreads / 64;
 
-// LDS float4 words of the register form: LR target cells (3 rows of nb + 2),
-// the code table (81 uint2), then the waves' sums (4 waves x nb cells x 9 C
-// floats, at most 4 x 64 x 9 float4).
-__host__ __device__ inline int reg_lds_words(int nb, int C) {
-  return 3 * (nb + 2) + (81 * 2 + 3) / 4 + (kRegWaves * nb * 9 * C + 3) / 4;
+struct RegGeom {
+  int cps, rw, sg, nbs, nb;
+};
+
+__host__ __device__ inline RegGeom reg_geom(int s, int P) {
+  RegGeom g;
+  g.cps = s / P;
+  g.rw = s < kRegWaves ? s : kRegWaves;
+  g.sg = kRegWaves / g.rw;
+  g.nbs = 64 / g.cps;
+  g.nb = g.sg * g.nbs;
+  return g;
 }
 
-template <typename T, int C>
+// LDS float4 words of the register form: LR target cells (3 rows of nb + 2),
+// the code table (81 uint2), then the row groups' sums (RW x nb cells x 9 C
+// floats).
+__host__ __device__ inline int reg_lds_words(const RegGeom& g, int C) {
+  return 3 * (g.nb + 2) + (81 * 2 + 3) / 4 + (g.rw * g.nb * 9 * C + 3) / 4;
+}
+
+template <typename T, int C, int P>
 __global__ __launch_bounds__(kThreads) void k_bwd_reg(const BwdArgs a0) {
   extern __shared__ float4 smem[];
   const BwdArgs a = batch_image<T>(a0);
-  const int s = a.s, cps = s >> 2, nb = a.nb;
+  const int s = a.s;
+  const RegGeom gm = reg_geom(s, P);
+  const int cps = gm.cps, nb = gm.nb, nbs = gm.nbs, RW = gm.rw;
   const int qy = blockIdx.x / a.groups_x;
   const int qx0 = (blockIdx.x - qy * a.groups_x) * nb;
   const int lx = nb + 2;
@@ -358,6 +379,7 @@ __global__ __launch_bounds__(kThreads) void k_bwd_reg(const BwdArgs a0) {
   float* sSum = reinterpret_cast<float*>(sT + 3 * lx + (81 * 2 + 3) / 4);
   const int tid = (int)threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
+  const int seg = wave / RW, rg = wave - seg * RW;
   const T* __restrict__ TL = static_cast<const T*>(a.T);
 
   // code -> (LDS offsets of the cells a and b relative to the pixel's cell
@@ -379,11 +401,14 @@ __global__ __launch_bounds__(kThreads) void k_bwd_reg(const BwdArgs a0) {
   }
   __syncthreads();
 
-  const bool vecTh = (a.vec & VEC_THETA) != 0, vecG = (a.vec & VEC_G) != 0, vecA = (a.vec & VEC_T) != 0;
-  const int cl = lane / cps;
-  const int x = qx0 * s + 4 * lane;
-  const bool active = lane < nb * cps && x < a.W;  // x < W also keeps the cell inside the image
-  const bool full = x + 4 <= a.W;
+  const bool vecTh = P == 4 && (a.vec & VEC_THETA) != 0, vecG = P == 4 && (a.vec & VEC_G) != 0,
+             vecA = P == 4 && (a.vec & VEC_T) != 0;
+  const int cls = lane / cps;            // cell in the segment
+  const int cl = seg * nbs + cls;        // cell in the workgroup
+  const int x = (qx0 + seg * nbs) * s + P * lane;
+  const bool mine = seg < gm.sg && lane < nbs * cps;  // the lane owns a column of a cell
+  const bool active = mine && x < a.W;               // x < W also keeps the cell inside the image
+  const bool full = x + P <= a.W;
   float acc[9][C];
 #pragma unroll
   for (int o = 0; o < 9; ++o)
@@ -392,34 +417,39 @@ __global__ __launch_bounds__(kThreads) void k_bwd_reg(const BwdArgs a0) {
 
   if (active) {
     const int y1 = min(a.H, (qy + 1) * s);
-    for (int y = qy * s + wave; y < y1; y += kRegWaves) {
+    for (int y = qy * s + rg; y < y1; y += RW) {
       const int64_t to = (int64_t)y * a.th_stride + x;
-      int cd[4];
-      float al[4];
-      if (vecTh && full) {
-        const u32x2 c = __builtin_nontemporal_load(reinterpret_cast<const u32x2*>(a.code + to));
-        const f32x4 a4 = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(a.alpha + to));
-        cd[0] = c.x & 0xffff;
-        cd[1] = c.x >> 16;
-        cd[2] = c.y & 0xffff;
-        cd[3] = c.y >> 16;
-        al[0] = a4.x;
-        al[1] = a4.y;
-        al[2] = a4.z;
-        al[3] = a4.w;
-      } else {
+      int cd[P];
+      float al[P];
+      bool done = false;
+      if constexpr (P == 4) {
+        if (vecTh && full) {
+          const u32x2 c = __builtin_nontemporal_load(reinterpret_cast<const u32x2*>(a.code + to));
+          const f32x4 a4 = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(a.alpha + to));
+          cd[0] = c.x & 0xffff;
+          cd[1] = c.x >> 16;
+          cd[2] = c.y & 0xffff;
+          cd[3] = c.y >> 16;
+          al[0] = a4.x;
+          al[1] = a4.y;
+          al[2] = a4.z;
+          al[3] = a4.w;
+          done = true;
+        }
+      }
+      if (!done) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < P; ++q) {
           const bool ok = full || (x + q < a.W);
           cd[q] = ok ? a.code[to + q] : 0;
           al[q] = ok ? a.alpha[to + q] : 0.f;
         }
       }
-      float g[4][4];
-      load_grad<4>(a.G + (int64_t)y * a.G_stride, x, a.W, C, vecG, full, g);  // zero past the image
-      float da[4];
+      float g[P][4];
+      load_grad<P>(a.G + (int64_t)y * a.G_stride, x, a.W, C, vecG, full, g);  // zero past the image
+      float da[P];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
+      for (int q = 0; q < P; ++q) {
         const uint2 e = sDec[min(cd[q], 80)];
         da[q] = 0.f;
         if (a.dalpha) {
@@ -442,11 +472,16 @@ __global__ __launch_bounds__(kThreads) void k_bwd_reg(const BwdArgs a0) {
         }
       }
       if (a.dalpha) {
-        if (vecA && full) {
-          __builtin_nontemporal_store(f32x4{da[0], da[1], da[2], da[3]}, reinterpret_cast<f32x4*>(a.dalpha + to));
-        } else {
+        bool st = false;
+        if constexpr (P == 4) {
+          if (vecA && full) {
+            __builtin_nontemporal_store(f32x4{da[0], da[1], da[2], da[3]}, reinterpret_cast<f32x4*>(a.dalpha + to));
+            st = true;
+          }
+        }
+        if (!st) {
 #pragma unroll
-          for (int q = 0; q < 4; ++q)
+          for (int q = 0; q < P; ++q)
             if (full || x + q < a.W) a.dalpha[to + q] = da[q];
         }
       }
@@ -464,7 +499,7 @@ __global__ __launch_bounds__(kThreads) void k_bwd_reg(const BwdArgs a0) {
         for (int ch = 0; ch < C; ++ch) acc[o][ch] += __shfl_xor(acc[o][ch], m, 64);
     }
   } else {
-    const int first = min(cl, nb - 1) * cps;
+    const int first = min(cls, nbs - 1) * cps;
 #pragma unroll
     for (int o = 0; o < 9; ++o)
 #pragma unroll
@@ -474,8 +509,8 @@ __global__ __launch_bounds__(kThreads) void k_bwd_reg(const BwdArgs a0) {
         acc[o][ch] = v;
       }
   }
-  if (lane < nb * cps && lane % cps == 0) {
-    float* dst = sSum + ((wave * nb + cl) * 9) * C;
+  if (mine && lane % cps == 0) {
+    float* dst = sSum + ((rg * nb + cl) * 9) * C;
 #pragma unroll
     for (int o = 0; o < 9; ++o)
 #pragma unroll
@@ -489,31 +524,36 @@ __global__ __launch_bounds__(kThreads) void k_bwd_reg(const BwdArgs a0) {
     float v[C];
 #pragma unroll
     for (int ch = 0; ch < C; ++ch) v[ch] = 0.f;
+    for (int r = 0; r < RW; ++r)
 #pragma unroll
-    for (int wv = 0; wv < kRegWaves; ++wv)
-#pragma unroll
-      for (int ch = 0; ch < C; ++ch) v[ch] += sSum[((wv * nb + c) * 9 + o) * C + ch];
+      for (int ch = 0; ch < C; ++ch) v[ch] += sSum[((r * nb + c) * 9 + o) * C + ch];
     float* out = a.S + ((int64_t)o * hw + (int64_t)qy * a.w + qx0 + c) * C;
 #pragma unroll
     for (int ch = 0; ch < C; ++ch) out[ch] = v[ch];
   }
 }
 
-static BwdKernel pick_reg(bool f16, int C) {
+template <int P>
+static BwdKernel pick_reg_p(bool f16, int C) {
   switch (C) {
-    case 1: return f16 ? k_bwd_reg<__half, 1> : k_bwd_reg<float, 1>;
-    case 2: return f16 ? k_bwd_reg<__half, 2> : k_bwd_reg<float, 2>;
-    case 3: return f16 ? k_bwd_reg<__half, 3> : k_bwd_reg<float, 3>;
-    default: return f16 ? k_bwd_reg<__half, 4> : k_bwd_reg<float, 4>;
+    case 1: return f16 ? k_bwd_reg<__half, 1, P> : k_bwd_reg<float, 1, P>;
+    case 2: return f16 ? k_bwd_reg<__half, 2, P> : k_bwd_reg<float, 2, P>;
+    case 3: return f16 ? k_bwd_reg<__half, 3, P> : k_bwd_reg<float, 3, P>;
+    default: return f16 ? k_bwd_reg<__half, 4, P> : k_bwd_reg<float, 4, P>;
   }
 }
 
-// The register form covers 3 x 3 windows with s a multiple of 4 up to
-// 256: the 64 lanes of a wave span nb = floor(256 / s) cells.
-static bool reg_geometry(int s, int k, int& nb) {
-  if (k != 3 || s % 4 != 0 || s > 256) return false;
-  nb = 256 / s;
-  return true;
+static BwdKernel pick_reg(bool f16, int C, int P) {
+  if (P == 4) return pick_reg_p<4>(f16, C);
+  if (P == 3) return pick_reg_p<3>(f16, C);
+  return pick_reg_p<2>(f16, C);
+}
+
+// The register form covers 3 x 3 windows whose s has a strip width P of 4,
+// 3 or 2 pixels with s / P <= 64 lanes per cell row.
+static bool reg_geometry(int s, int k, int& P) {
+  P = strip_pixels(s);
+  return k == 3 && P >= 2 && s / P <= 64;
 }
 
 template <int KW, int C>
@@ -641,11 +681,15 @@ static glu_status backward_batched(int32_t n, const glu_batch_strides* bs, const
     a.b_dT = bs->grad_T_low;
     a.b_S = (int64_t)(glu_apply_backward_workspace(H, W, C, p) / sizeof(float));
   }
-  const bool reg = reg_geometry(p->s, p->k, a.nb);
-  if (!reg) bwd_geometry(p->s, p->k, w, a.nb, a.rows_chunk);
+  int regP = 0;
+  const bool reg = reg_geometry(p->s, p->k, regP);
+  if (reg)
+    a.nb = reg_geom(p->s, regP).nb;
+  else
+    bwd_geometry(p->s, p->k, w, a.nb, a.rows_chunk);
   a.groups_x = ceil_div(w, a.nb);
   a.s_magic = (uint32_t)std::min<uint64_t>(0xffffffffull, (1ull << 32) / (uint64_t)p->s);
-  const int P = (p->s % 4 == 0) ? 4 : 1;
+  const int P = reg ? regP : ((p->s % 4 == 0) ? 4 : 1);
   {
     // alignment of the vector paths (all with x a multiple of 4), for every
     // image of the batch
@@ -659,11 +703,11 @@ static glu_status backward_batched(int32_t n, const glu_batch_strides* bs, const
       v |= VEC_G;
     a.vec = v;
   }
-  const size_t lds = (size_t)16 * (reg ? reg_lds_words(a.nb, C) : bwd_lds_words(p->k, a.nb, p->s, a.rows_chunk));
+  const size_t lds = (size_t)16 * (reg ? reg_lds_words(reg_geom(p->s, regP), C) : bwd_lds_words(p->k, a.nb, p->s, a.rows_chunk));
   const int64_t groups = (int64_t)h * a.groups_x;
   if (groups > 0x7fffffff) return fail(GLU_ERR_UNSUPPORTED, "image too large");
   hipStream_t sm = (hipStream_t)stream;
-  BwdKernel kern = reg ? pick_reg(T_low->dtype == GLU_F16, C) : pick_bwd(T_low->dtype == GLU_F16, P, p->k, C);
+  BwdKernel kern = reg ? pick_reg(T_low->dtype == GLU_F16, C, regP) : pick_bwd(T_low->dtype == GLU_F16, P, p->k, C);
   hipLaunchKernelGGL(kern, dim3((unsigned)groups, (unsigned)n), dim3(kThreads), lds, sm, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "backward pass 1 launch");

@@ -93,6 +93,12 @@ def _check(glu, H, W, s, k, C, seed, t_dtype=torch.float32):
         (100, 130, 20, 3, 2),
         (520, 300, 256, 3, 3),
         (24, 20, 512, 3, 3),
+        (64, 90, 2, 3, 3),
+        (31, 47, 3, 3, 3),
+        (70, 100, 6, 3, 1),
+        (55, 73, 10, 3, 3),
+        (60, 80, 9, 3, 2),
+        (29, 41, 2, 3, 4),
     ],
 )
 def test_backward_parity(H, W, s, k, C):
@@ -182,7 +188,8 @@ def test_autograd_function_matches_torch_reference():
     np.testing.assert_allclose(host(T_t.grad).reshape(-1, 3), Tr.grad.numpy(), rtol=1e-4, atol=1e-9)
 
 
-@pytest.mark.parametrize("H,W,s,k,C,step", [(96, 136, 8, 3, 3, 1), (50, 70, 4, 5, 2, 2), (33, 29, 3, 3, 1, 1)])
+@pytest.mark.parametrize("H,W,s,k,C,step", [(96, 136, 8, 3, 3, 1), (50, 70, 4, 5, 2, 2), (33, 29, 3, 3, 1, 1),
+                                              (40, 62, 2, 3, 3, 1)])
 def test_batched_apply_and_backward_equal_per_image(H, W, s, k, C, step):
     """glu_apply_batched / glu_apply_backward_batched give bitwise the results
     of per-image calls, also for a strided view of a larger batch."""
