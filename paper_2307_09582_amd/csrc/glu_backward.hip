@@ -13,11 +13,11 @@
 //     block of the part of their contribution aimed at the cell
 //     c + offset(o).  dL/dalpha is computed from LR target cells staged in
 //     LDS and written on the way.  Two forms, both with fixed orders:
-//     * registers (3 x 3 windows, s with a strip width of 4, 3 or 2
-//       pixels): a lane owns a column of P pixels of a cell's block and
-//       every RW-th HR row of it, and keeps 9 C sums (window offset,
-//       channel) in registers; the lanes of a cell, then the row groups,
-//       add theirs in a fixed order.
+//     * registers (3 x 3 windows with a strip width of 4, 3 or 2 pixels,
+//       5 x 5 windows with 4): a lane owns a column of P pixels of a cell's
+//       block and every RW-th HR row of it, and keeps k^2 C sums (window
+//       offset, channel) in registers; the lanes of a cell, then the row
+//       groups, add theirs in a fixed order.
 //     * scan (every other shape): a workgroup owns nb consecutive cells of
 //       one LR row (nb * k^2 <= 256), streams chunks of its HR rows into
 //       LDS, and one lane per (cell, offset) scans the chunk's pixels of
@@ -328,74 +328,79 @@ static BwdKernel pick_bwd(bool f16, int P, int k, int C) {
   return P == 4 ? pick_bwd_k<float, 4>(k, C) : pick_bwd_k<float, 1>(k, C);
 }
 
-// Register form of pass 1 (k = 3; strips of P = 4, 3 or 2 pixels, P the
-// largest of them that divides s; cps = s / P lanes per cell row, at most
-// 64).  The four waves of a workgroup form RW = min(4, s) row groups times
-// SG = 4 / RW column segments (for s = 3 the fourth wave idles).  A
-// segment holds nbs = floor(64 / cps) cells of LR row qy, and the
-// workgroup nb = SG nbs of them.  Wave v takes segment v / RW and the HR
-// rows y0 + (v mod RW) + RW i; lane l the pixels P l .. P l + P - 1 of the
-// segment, all in the segment's cell l / cps.  Each lane keeps 9 C sums in
-// registers, one per window offset and channel: a pixel adds alpha G where
-// o_a = o and (1 - alpha) G where o_b = o.  The first lane of a cell adds
-// up the sums of its cps lanes (cross-lane reads in a fixed order), the
-// row groups' sums meet in LDS, and one lane per (offset, cell) adds them in
-// row-group order and writes S.
+// Register form of pass 1 (k = 3 with strips of P = 4, 3 or 2 pixels, P
+// the largest of them that divides s; k = 5 with P = 4; cps = s / P lanes
+// per cell row, at most 64).  The four waves of a workgroup form RW row
+// groups times SG = 4 / RW column segments: RW = min(4, s) (for s = 3 the
+// fourth wave idles), except RW = 1 for k = 5 with s < 16.  A segment holds nbs = floor(64 / cps)
+// cells of LR row qy, and the workgroup nb = SG nbs of them.  Wave v takes
+// segment v / RW and the HR rows y0 + (v mod RW) + RW i; lane l the pixels
+// P l .. P l + P - 1 of the segment, all in the segment's cell l / cps.
+// Each lane keeps k^2 C sums in registers, one per window offset and
+// channel: a pixel adds alpha G where o_a = o and (1 - alpha) G where
+// o_b = o.  The first lane of a cell adds up the sums of its cps lanes
+// (cross-lane reads in a fixed order).  With one row group it writes S
+// itself; otherwise the row groups' sums meet in LDS, and one lane per
+// (offset, cell) adds them in row-group order and writes S.
 constexpr int kRegWaves = kThreads / 64;
 
 struct RegGeom {
   int cps, rw, sg, nbs, nb;
 };
 
-__host__ __device__ inline RegGeom reg_geom(int s, int P) {
+__host__ __device__ inline RegGeom reg_geom(int s, int P, int k) {
   RegGeom g;
   g.cps = s / P;
-  g.rw = s < kRegWaves ? s : kRegWaves;
+  // k = 5: one row group up to s = 8 (its 25 C sums per lane in four row
+  // groups would need too much LDS there), four from s = 16 on
+  g.rw = (k == 3 || s >= 16) ? (s < kRegWaves ? s : kRegWaves) : 1;
   g.sg = kRegWaves / g.rw;
   g.nbs = 64 / g.cps;
   g.nb = g.sg * g.nbs;
   return g;
 }
 
-// LDS float4 words of the register form: LR target cells (3 rows of nb + 2),
-// the code table (81 uint2), then the row groups' sums (RW x nb cells x 9 C
-// floats).
-__host__ __device__ inline int reg_lds_words(const RegGeom& g, int C) {
-  return 3 * (g.nb + 2) + (81 * 2 + 3) / 4 + (g.rw * g.nb * 9 * C + 3) / 4;
+// LDS float4 words of the register form: LR target cells (k rows of
+// nb + k - 1), the code table (k^4 uint2), then, with several row groups,
+// their sums (RW x nb cells x k^2 C floats).
+__host__ __device__ inline int reg_lds_words(const RegGeom& g, int k, int C) {
+  const int K2 = k * k;
+  return k * (g.nb + k - 1) + (K2 * K2 * 2 + 3) / 4 + (g.rw > 1 ? (g.rw * g.nb * K2 * C + 3) / 4 : 0);
 }
 
-template <typename T, int C, int P>
+template <typename T, int C, int P, int KW>
 __global__ __launch_bounds__(kThreads) void k_bwd_reg(const BwdArgs a0) {
   extern __shared__ float4 smem[];
+  constexpr int K2 = KW * KW, R = KW / 2;
   const BwdArgs a = batch_image<T>(a0);
   const int s = a.s;
-  const RegGeom gm = reg_geom(s, P);
+  const RegGeom gm = reg_geom(s, P, KW);
   const int cps = gm.cps, nb = gm.nb, nbs = gm.nbs, RW = gm.rw;
   const int qy = blockIdx.x / a.groups_x;
   const int qx0 = (blockIdx.x - qy * a.groups_x) * nb;
-  const int lx = nb + 2;
+  const int lx = nb + KW - 1;
   float4* sT = smem;
-  uint2* sDec = reinterpret_cast<uint2*>(sT + 3 * lx);
-  float* sSum = reinterpret_cast<float*>(sT + 3 * lx + (81 * 2 + 3) / 4);
+  uint2* sDec = reinterpret_cast<uint2*>(sT + KW * lx);
+  float* sSum = reinterpret_cast<float*>(sT + KW * lx + (K2 * K2 * 2 + 3) / 4);
   const int tid = (int)threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int seg = wave / RW, rg = wave - seg * RW;
   const T* __restrict__ TL = static_cast<const T*>(a.T);
 
-  // code -> (LDS offsets of the cells a and b relative to the pixel's cell
-  // at window offset 0, window offsets o_a and o_b)
-  for (int c = tid; c < 81; c += kThreads) {
-    const int oa = c / 9, ob = c - oa * 9;
-    sDec[c] = make_uint2((uint32_t)((oa / 3) * lx + oa % 3) | ((uint32_t)((ob / 3) * lx + ob % 3) << 16),
+  // code -> (LDS offsets of the cells a and b relative to the pixel's
+  // window corner, window offsets o_a and o_b)
+  for (int c = tid; c < K2 * K2; c += kThreads) {
+    const int oa = c / K2, ob = c - oa * K2;
+    sDec[c] = make_uint2((uint32_t)((oa / KW) * lx + oa % KW) | ((uint32_t)((ob / KW) * lx + ob % KW) << 16),
                          (uint32_t)oa | ((uint32_t)ob << 16));
   }
   if (a.dalpha) {
-    // rows qy - 1 .. qy + 1, columns qx0 - 1 .. qx0 + nb, clamped to the LR
-    // image (codes from the search never leave it)
-    for (int i = tid; i < 3 * lx; i += kThreads) {
+    // rows qy - R .. qy + R, columns qx0 - R .. qx0 + nb - 1 + R, clamped to
+    // the LR image (codes from the search never leave it)
+    for (int i = tid; i < KW * lx; i += kThreads) {
       const int rr = i / lx, c = i - rr * lx;
-      const int cy = min(max(qy - 1 + rr, 0), a.h - 1);
-      const int cx = min(max(qx0 - 1 + c, 0), a.w - 1);
+      const int cy = min(max(qy - R + rr, 0), a.h - 1);
+      const int cx = min(max(qx0 - R + c, 0), a.w - 1);
       sT[i] = load_cell<T>(TL + (int64_t)cy * a.T_stride + (int64_t)cx * C, C);
     }
   }
@@ -409,9 +414,9 @@ __global__ __launch_bounds__(kThreads) void k_bwd_reg(const BwdArgs a0) {
   const bool mine = seg < gm.sg && lane < nbs * cps;  // the lane owns a column of a cell
   const bool active = mine && x < a.W;               // x < W also keeps the cell inside the image
   const bool full = x + P <= a.W;
-  float acc[9][C];
+  float acc[K2][C];
 #pragma unroll
-  for (int o = 0; o < 9; ++o)
+  for (int o = 0; o < K2; ++o)
 #pragma unroll
     for (int ch = 0; ch < C; ++ch) acc[o][ch] = 0.f;
 
@@ -450,7 +455,7 @@ __global__ __launch_bounds__(kThreads) void k_bwd_reg(const BwdArgs a0) {
       float da[P];
 #pragma unroll
       for (int q = 0; q < P; ++q) {
-        const uint2 e = sDec[min(cd[q], 80)];
+        const uint2 e = sDec[min(cd[q], K2 * K2 - 1)];
         da[q] = 0.f;
         if (a.dalpha) {
           const float4 Ta = sT[cl + (e.x & 0xffff)];
@@ -464,7 +469,7 @@ __global__ __launch_bounds__(kThreads) void k_bwd_reg(const BwdArgs a0) {
         if (a.S) {
           const int oa = (int)(e.y & 0xffff), ob = (int)(e.y >> 16);
 #pragma unroll
-          for (int o = 0; o < 9; ++o) {
+          for (int o = 0; o < K2; ++o) {
             const float wt = (oa == o ? al[q] : 0.0f) + (ob == o ? 1.0f - al[q] : 0.0f);
 #pragma unroll
             for (int ch = 0; ch < C; ++ch) acc[o][ch] = fmaf(wt, g[q][ch], acc[o][ch]);
@@ -494,14 +499,14 @@ __global__ __launch_bounds__(kThreads) void k_bwd_reg(const BwdArgs a0) {
   if ((cps & (cps - 1)) == 0) {
     for (int m = 1; m < cps; m <<= 1) {
 #pragma unroll
-      for (int o = 0; o < 9; ++o)
+      for (int o = 0; o < K2; ++o)
 #pragma unroll
         for (int ch = 0; ch < C; ++ch) acc[o][ch] += __shfl_xor(acc[o][ch], m, 64);
     }
   } else {
     const int first = min(cls, nbs - 1) * cps;
 #pragma unroll
-    for (int o = 0; o < 9; ++o)
+    for (int o = 0; o < K2; ++o)
 #pragma unroll
       for (int ch = 0; ch < C; ++ch) {
         float v = __shfl(acc[o][ch], first, 64);
@@ -509,51 +514,66 @@ __global__ __launch_bounds__(kThreads) void k_bwd_reg(const BwdArgs a0) {
         acc[o][ch] = v;
       }
   }
-  if (mine && lane % cps == 0) {
-    float* dst = sSum + ((rg * nb + cl) * 9) * C;
+  const int64_t hw = (int64_t)a.h * a.w;
+  if (RW == 1) {
+    // one row group: the cell's first lane holds the whole sum
+    if (active && lane % cps == 0) {
+      float* out = a.S + ((int64_t)qy * a.w + qx0 + cl) * C;
 #pragma unroll
-    for (int o = 0; o < 9; ++o)
+      for (int o = 0; o < K2; ++o)
+#pragma unroll
+        for (int ch = 0; ch < C; ++ch) out[(int64_t)o * hw * C + ch] = acc[o][ch];
+    }
+    return;
+  }
+  if (mine && lane % cps == 0) {
+    float* dst = sSum + ((rg * nb + cl) * K2) * C;
+#pragma unroll
+    for (int o = 0; o < K2; ++o)
 #pragma unroll
       for (int ch = 0; ch < C; ++ch) dst[o * C + ch] = acc[o][ch];
   }
   __syncthreads();
-  const int64_t hw = (int64_t)a.h * a.w;
   const int nbv = min(nb, a.w - qx0);
-  for (int i = tid; i < 9 * nbv; i += kThreads) {
+  for (int i = tid; i < K2 * nbv; i += kThreads) {
     const int o = i / nbv, c = i - o * nbv;
     float v[C];
 #pragma unroll
     for (int ch = 0; ch < C; ++ch) v[ch] = 0.f;
     for (int r = 0; r < RW; ++r)
 #pragma unroll
-      for (int ch = 0; ch < C; ++ch) v[ch] += sSum[((r * nb + c) * 9 + o) * C + ch];
+      for (int ch = 0; ch < C; ++ch) v[ch] += sSum[((r * nb + c) * K2 + o) * C + ch];
     float* out = a.S + ((int64_t)o * hw + (int64_t)qy * a.w + qx0 + c) * C;
 #pragma unroll
     for (int ch = 0; ch < C; ++ch) out[ch] = v[ch];
   }
 }
 
-template <int P>
+template <int P, int KW>
 static BwdKernel pick_reg_p(bool f16, int C) {
   switch (C) {
-    case 1: return f16 ? k_bwd_reg<__half, 1, P> : k_bwd_reg<float, 1, P>;
-    case 2: return f16 ? k_bwd_reg<__half, 2, P> : k_bwd_reg<float, 2, P>;
-    case 3: return f16 ? k_bwd_reg<__half, 3, P> : k_bwd_reg<float, 3, P>;
-    default: return f16 ? k_bwd_reg<__half, 4, P> : k_bwd_reg<float, 4, P>;
+    case 1: return f16 ? k_bwd_reg<__half, 1, P, KW> : k_bwd_reg<float, 1, P, KW>;
+    case 2: return f16 ? k_bwd_reg<__half, 2, P, KW> : k_bwd_reg<float, 2, P, KW>;
+    case 3: return f16 ? k_bwd_reg<__half, 3, P, KW> : k_bwd_reg<float, 3, P, KW>;
+    default: return f16 ? k_bwd_reg<__half, 4, P, KW> : k_bwd_reg<float, 4, P, KW>;
   }
 }
 
-static BwdKernel pick_reg(bool f16, int C, int P) {
-  if (P == 4) return pick_reg_p<4>(f16, C);
-  if (P == 3) return pick_reg_p<3>(f16, C);
-  return pick_reg_p<2>(f16, C);
+static BwdKernel pick_reg(bool f16, int C, int P, int k) {
+  if (k == 5) return pick_reg_p<4, 5>(f16, C);
+  if (P == 4) return pick_reg_p<4, 3>(f16, C);
+  if (P == 3) return pick_reg_p<3, 3>(f16, C);
+  return pick_reg_p<2, 3>(f16, C);
 }
 
 // The register form covers 3 x 3 windows whose s has a strip width P of 4,
-// 3 or 2 pixels with s / P <= 64 lanes per cell row.
-static bool reg_geometry(int s, int k, int& P) {
+// 3 or 2 pixels, and 5 x 5 windows with P = 4; s / P <= 64 lanes per cell
+// row.
+static bool reg_geometry(int s, int k, int C, int& P) {
   P = strip_pixels(s);
-  return k == 3 && P >= 2 && s / P <= 64;
+  if (s / P > 64) return false;
+  if (!((k == 3 && P >= 2) || (k == 5 && P == 4))) return false;
+  return 16 * reg_lds_words(reg_geom(s, P, k), k, C) <= 64 * 1024;
 }
 
 template <int KW, int C>
@@ -682,9 +702,9 @@ static glu_status backward_batched(int32_t n, const glu_batch_strides* bs, const
     a.b_S = (int64_t)(glu_apply_backward_workspace(H, W, C, p) / sizeof(float));
   }
   int regP = 0;
-  const bool reg = reg_geometry(p->s, p->k, regP);
+  const bool reg = reg_geometry(p->s, p->k, C, regP);
   if (reg)
-    a.nb = reg_geom(p->s, regP).nb;
+    a.nb = reg_geom(p->s, regP, p->k).nb;
   else
     bwd_geometry(p->s, p->k, w, a.nb, a.rows_chunk);
   a.groups_x = ceil_div(w, a.nb);
@@ -703,11 +723,11 @@ static glu_status backward_batched(int32_t n, const glu_batch_strides* bs, const
       v |= VEC_G;
     a.vec = v;
   }
-  const size_t lds = (size_t)16 * (reg ? reg_lds_words(reg_geom(p->s, regP), C) : bwd_lds_words(p->k, a.nb, p->s, a.rows_chunk));
+  const size_t lds = (size_t)16 * (reg ? reg_lds_words(reg_geom(p->s, regP, p->k), p->k, C) : bwd_lds_words(p->k, a.nb, p->s, a.rows_chunk));
   const int64_t groups = (int64_t)h * a.groups_x;
   if (groups > 0x7fffffff) return fail(GLU_ERR_UNSUPPORTED, "image too large");
   hipStream_t sm = (hipStream_t)stream;
-  BwdKernel kern = reg ? pick_reg(T_low->dtype == GLU_F16, C, regP) : pick_bwd(T_low->dtype == GLU_F16, P, p->k, C);
+  BwdKernel kern = reg ? pick_reg(T_low->dtype == GLU_F16, C, regP, p->k) : pick_bwd(T_low->dtype == GLU_F16, P, p->k, C);
   hipLaunchKernelGGL(kern, dim3((unsigned)groups, (unsigned)n), dim3(kThreads), lds, sm, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "backward pass 1 launch");

@@ -99,6 +99,11 @@ def _check(glu, H, W, s, k, C, seed, t_dtype=torch.float32):
         (55, 73, 10, 3, 3),
         (60, 80, 9, 3, 2),
         (29, 41, 2, 3, 4),
+        (72, 100, 4, 5, 3),
+        (64, 80, 8, 5, 4),
+        (96, 96, 16, 5, 2),
+        (50, 70, 12, 5, 1),
+        (41, 67, 8, 5, 3),
     ],
 )
 def test_backward_parity(H, W, s, k, C):
