@@ -2,7 +2,8 @@
 //
 // A plan holds a device table of image descriptors (any mix of sizes,
 // ratios s, windows k and storage types), grouped by kernel variant (window
-// class, pixels per strip, storage type), each group with the prefix sum of
+// class, pixels per strip, storage type, pair table or none), each group
+// with the prefix sum of
 // its tile counts.  One launch of a kernel specialised for the group's
 // variant runs fused search + apply over all of the group's images, one
 // workgroup per tile: workgroup g finds the image of tile g by binary search
