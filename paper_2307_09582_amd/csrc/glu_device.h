@@ -214,9 +214,11 @@ __device__ __forceinline__ float pair_err2(float dx, float dy, float dz, float a
 // and .w = 0 outside.
 //   LdsWin     - the tile's staged copy in LDS (window top-left at p, row
 //                pitch lx);
-//   GlobalWin  - straight from the LR guide in global memory, bypassing the
-//                vector L1 cache so that colours another thread of the same
-//                workgroup just rewrote are seen (joint downsampling).
+//   GlobalWin  - straight from the LR guide in global memory, with coherent
+//                (L1-bypassing) loads so that colours another thread of the
+//                same workgroup just rewrote are seen (joint downsampling);
+//   RegWin     - a k x k window (compile-time k) read once from a GlobalWin
+//                into registers.
 template <int KW>
 struct LdsWin {
   const float4* __restrict__ p;
@@ -235,9 +237,23 @@ struct GlobalWin {
   __device__ __forceinline__ float4 operator()(int o) const {
     const int cy = qy + o / kw - r, cx = qx + o % kw - r;
     if (cy < 0 || cy >= h || cx < 0 || cx >= w) return make_float4(0.f, 0.f, 0.f, 0.f);
-    const volatile float* q = L + (int64_t)cy * Ls + (int64_t)cx * 3;
-    return make_float4(q[0], q[1], q[2], 1.0f);
+    const float* q = L + (int64_t)cy * Ls + (int64_t)cx * 3;
+    // relaxed agent-scope atomic loads: coherent, yet free to be issued
+    // together (volatile ones would each wait for the previous)
+    return make_float4(__hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+                       __hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+                       __hip_atomic_load(q + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), 1.0f);
   }
+};
+
+template <int KW>
+struct RegWin {
+  float4 c[KW * KW];
+  __device__ __forceinline__ explicit RegWin(const GlobalWin& g) {
+#pragma unroll
+    for (int o = 0; o < KW * KW; ++o) c[o] = g(o);
+  }
+  __device__ __forceinline__ float4 operator()(int o) const { return c[o]; }
 };
 
 // ---------------------------------------------------------------------------

@@ -82,53 +82,59 @@ __global__ __launch_bounds__(256) void k_jd_mark(const float* __restrict__ E, in
   if (threadIdx.x == 0) tile_count[blockIdx.x] = wcount[0] + wcount[1] + wcount[2] + wcount[3];
 }
 
-// exclusive scan of the tile counts by one workgroup (running carry)
+// exclusive scan of the tile counts by one workgroup: each thread sums a
+// contiguous run of tiles, thread 0 scans the 256 run totals, and each
+// thread writes its run's offsets
 __global__ __launch_bounds__(256) void k_jd_scan(const int* __restrict__ cnt, int ntiles, int* __restrict__ off,
                                                  int* __restrict__ total) {
-  __shared__ int s[256];
-  __shared__ int carry;
-  if (threadIdx.x == 0) carry = 0;
+  __shared__ int run_sum[256];
+  const int per = (ntiles + 255) / 256;
+  const int t0 = min(ntiles, (int)threadIdx.x * per), t1 = min(ntiles, t0 + per);
+  int v = 0;
+  for (int i = t0; i < t1; ++i) v += cnt[i];
+  run_sum[threadIdx.x] = v;
   __syncthreads();
-  for (int b = 0; b < ntiles; b += 256) {
-    const int i = b + threadIdx.x;
-    const int v = i < ntiles ? cnt[i] : 0;
-    s[threadIdx.x] = v;
-    __syncthreads();
-    for (int d = 1; d < 256; d <<= 1) {
-      const int t = threadIdx.x >= d ? s[threadIdx.x - d] : 0;
-      __syncthreads();
-      s[threadIdx.x] += t;
-      __syncthreads();
+  if (threadIdx.x == 0) {
+    int acc = 0;
+    for (int i = 0; i < 256; ++i) {
+      const int c = run_sum[i];
+      run_sum[i] = acc;
+      acc += c;
     }
-    if (i < ntiles) off[i] = carry + s[threadIdx.x] - v;
-    __syncthreads();
-    if (threadIdx.x == 255) carry += s[255];
-    __syncthreads();
+    total[0] = acc;
   }
-  if (threadIdx.x == 0) total[0] = carry;
+  __syncthreads();
+  int acc = run_sum[threadIdx.x];
+  for (int i = t0; i < t1; ++i) {
+    const int c = cnt[i];
+    off[i] = acc;
+    acc += c;
+  }
 }
 
 // ordered scatter: pixel u*256 + tid of the tile goes after every marked
-// pixel of lower index in the tile
+// pixel of lower index in the tile (ranks from wave ballots)
 __global__ __launch_bounds__(256) void k_jd_scatter(const int* __restrict__ parent, int64_t n,
                                                     const int* __restrict__ tile_off, int* __restrict__ list) {
-  __shared__ int s[256];
+  __shared__ int wtot[2][4];
   const int64_t base = (int64_t)blockIdx.x * kTilePx;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const unsigned long long below = (1ull << lane) - 1ull;
   int run = tile_off[blockIdx.x];
   for (int u = 0; u < 4; ++u) {
     const int64_t p = base + u * 256 + threadIdx.x;
-    const int m = (p < n && parent[p] >= 0) ? 1 : 0;
-    s[threadIdx.x] = m;
+    const bool m = p < n && parent[p] >= 0;
+    const unsigned long long bal = __ballot(m);
+    if (lane == 0) wtot[u & 1][wave] = __popcll(bal);
     __syncthreads();
-    for (int d = 1; d < 256; d <<= 1) {
-      const int t = threadIdx.x >= d ? s[threadIdx.x - d] : 0;
-      __syncthreads();
-      s[threadIdx.x] += t;
-      __syncthreads();
+    int before = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      const int c = wtot[u & 1][w];
+      before += w < wave ? c : 0;
+      tot += c;
     }
-    if (m) list[run + s[threadIdx.x] - 1] = (int)p;
-    const int tot = s[255];
-    __syncthreads();
+    if (m) list[run + before + __popcll(bal & below)] = (int)p;
     run += tot;
   }
 }
@@ -247,26 +253,43 @@ __device__ __forceinline__ double block_sum(double v, double* s) {
   return r;
 }
 
+// One pixel's search against the current LR guide.  For 3 x 3 windows the
+// nine cells are read once into registers; other windows read them from
+// global memory as the candidate loops need them.
+template <int KW>
 __device__ __forceinline__ void search_one(const JdTrialArgs& a, int y, int x, int& code, float& al, float& e) {
   const float* ipp = a.I + (int64_t)y * a.I_stride + (int64_t)x * 3;
   const float ip[1][3] = {{ipp[0], ipp[1], ipp[2]}};
   const int r = a.k / 2;
-  const GlobalWin win{a.L, a.L_stride, y / a.s, x / a.s, a.h, a.w, a.k, r};
+  const GlobalWin gw{a.L, a.L_stride, y / a.s, x / a.s, a.h, a.w, a.k, r};
   float best[1], alp[1];
   int cd[1];
-  if (a.mode == MODE_EXH) {
-    exh_strip<0, 1, true, false>(ip, win, nullptr, a.eps, a.k, false, best, cd);
-    alp[0] = exh_alpha<0, false>(ip[0], win, nullptr, a.eps, a.k, cd[0]);
-  } else {
-    fast_strip<0, 1, true>(ip, win, a.eps, a.k, a.gnu != 0, best, cd, alp);
-  }
+  auto run = [&](const auto& win) {
+    if (a.mode == MODE_EXH) {
+      exh_strip<KW, 1, true, false>(ip, win, nullptr, a.eps, a.k, false, best, cd);
+      alp[0] = exh_alpha<KW, false>(ip[0], win, nullptr, a.eps, a.k, cd[0]);
+    } else {
+      fast_strip<KW, 1, true>(ip, win, a.eps, a.k, a.gnu != 0, best, cd, alp);
+    }
+  };
+  if constexpr (KW == 3)
+    run(RegWin<3>(gw));
+  else
+    run(gw);
   code = cd[0];
   al = alp[0];
   e = __builtin_amdgcn_sqrtf(best[0]);
 }
 
+// affected cells of one trial listed in LDS (more fall back to the box walk)
+constexpr int kTrialCells = 4096;
+
+template <int KW>
 __global__ __launch_bounds__(256) void k_jd_trial(const JdTrialArgs a) {
   __shared__ double red[256];
+  __shared__ int s_cells[kTrialCells];
+  __shared__ int s_cnt[256];
+  __shared__ int s_naff;
   const int* cm = a.b.comp + 8 * (a.comp_begin + blockIdx.x);
   const int q_off = cm[2], n_q = cm[3], slot = cm[4];
   const int by0 = cm[5], bx0 = cm[6], by1 = cm[7] >> 16, bx1 = cm[7] & 0xffff;
@@ -290,16 +313,58 @@ __global__ __launch_bounds__(256) void k_jd_trial(const JdTrialArgs a) {
   __syncthreads();
 
   // affected pixels are enumerated as: cells of the box in raster order,
-  // flagged ones only, and each block's pixels in raster order
+  // flagged ones only, and each block's pixels in raster order.  The
+  // flagged cells are first compacted into an LDS list (each thread takes a
+  // contiguous run of the box); a component with more affected cells than
+  // the list holds walks the whole box instead.
   const int ss = s * s;
-  const int64_t nslots = (int64_t)bw * bh * ss;
+  const int nbox = bw * bh;
+  {
+    const int per = (nbox + 255) / 256;
+    const int c0 = min(nbox, (int)threadIdx.x * per), c1 = min(nbox, c0 + per);
+    int cnt = 0;
+    for (int c = c0; c < c1; ++c) {
+      const int cy = by0 + c / bw, cx = bx0 + c % bw;
+      cnt += __atomic_load_n(&a.b.flag[cy * a.w + cx], __ATOMIC_RELAXED) == mark;
+    }
+    s_cnt[threadIdx.x] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int acc = 0;
+      for (int i = 0; i < 256; ++i) {
+        const int v = s_cnt[i];
+        s_cnt[i] = acc;
+        acc += v;
+      }
+      s_naff = acc;
+    }
+    __syncthreads();
+    if (s_naff <= kTrialCells) {
+      int o = s_cnt[threadIdx.x];
+      for (int c = c0; c < c1; ++c) {
+        const int cy = by0 + c / bw, cx = bx0 + c % bw;
+        if (__atomic_load_n(&a.b.flag[cy * a.w + cx], __ATOMIC_RELAXED) == mark) s_cells[o++] = c;
+      }
+    }
+    __syncthreads();
+  }
+  const bool listed = s_naff <= kTrialCells;
+  const int64_t nslots = (int64_t)(listed ? s_naff : nbox) * ss;
+  // pixel (y, x) of slot t; false for a slot outside the affected set
+  auto slot_pixel = [&](int64_t t, int& y, int& x) -> bool {
+    const int k = (int)(t / ss), within = (int)(t - (int64_t)k * ss);
+    const int cell = listed ? s_cells[k] : k;
+    const int cy = by0 + cell / bw, cx = bx0 + cell % bw;
+    if (!listed && __atomic_load_n(&a.b.flag[cy * a.w + cx], __ATOMIC_RELAXED) != mark) return false;
+    y = cy * s + within / s;
+    x = cx * s + within % s;
+    return y < a.H && x < a.W;
+  };
+
   double e0 = 0.0;
   for (int64_t t = threadIdx.x; t < nslots; t += 256) {
-    const int cell = (int)(t / ss), within = (int)(t - (int64_t)cell * ss);
-    const int cy = by0 + cell / bw, cx = bx0 + cell % bw;
-    if (__atomic_load_n(&a.b.flag[cy * a.w + cx], __ATOMIC_RELAXED) != mark) continue;
-    const int y = cy * s + within / s, x = cx * s + within % s;
-    if (y >= a.H || x >= a.W) continue;
+    int y, x;
+    if (!slot_pixel(t, y, x)) continue;
     e0 += (double)a.b.E[(int64_t)y * a.W + x];
   }
   e0 = block_sum(e0, red);
@@ -335,14 +400,11 @@ __global__ __launch_bounds__(256) void k_jd_trial(const JdTrialArgs a) {
   // re-search the affected set into the staging buffers
   double e1 = 0.0;
   for (int64_t t = threadIdx.x; t < nslots; t += 256) {
-    const int cell = (int)(t / ss), within = (int)(t - (int64_t)cell * ss);
-    const int cy = by0 + cell / bw, cx = bx0 + cell % bw;
-    if (__atomic_load_n(&a.b.flag[cy * a.w + cx], __ATOMIC_RELAXED) != mark) continue;
-    const int y = cy * s + within / s, x = cx * s + within % s;
-    if (y >= a.H || x >= a.W) continue;
+    int y, x;
+    if (!slot_pixel(t, y, x)) continue;
     int cd;
     float al, e;
-    search_one(a, y, x, cd, al, e);
+    search_one<KW>(a, y, x, cd, al, e);
     const int64_t p = (int64_t)y * a.W + x;
     a.b.st_code[p] = (uint16_t)cd;
     a.b.st_alpha[p] = al;
@@ -355,11 +417,8 @@ __global__ __launch_bounds__(256) void k_jd_trial(const JdTrialArgs a) {
   // commit or roll back; clear the flags
   if (accept) {
     for (int64_t t = threadIdx.x; t < nslots; t += 256) {
-      const int cell = (int)(t / ss), within = (int)(t - (int64_t)cell * ss);
-      const int cy = by0 + cell / bw, cx = bx0 + cell % bw;
-      if (__atomic_load_n(&a.b.flag[cy * a.w + cx], __ATOMIC_RELAXED) != mark) continue;
-      const int y = cy * s + within / s, x = cx * s + within % s;
-      if (y >= a.H || x >= a.W) continue;
+      int y, x;
+      if (!slot_pixel(t, y, x)) continue;
       const int64_t p = (int64_t)y * a.W + x;
       const int64_t to = (int64_t)y * a.th_stride + x;
       a.code[to] = a.b.st_code[p];
@@ -436,13 +495,44 @@ static JdLayout jd_layout(int64_t H, int64_t W, int s) {
   return L;
 }
 
+// Page-locked host staging (hipHostMalloc) for the small per-round copies:
+// copies to or from pageable memory are staged by the runtime and stall the
+// host.  One buffer per thread and purpose, grown on demand and kept until
+// the process ends; every use ends with a stream synchronisation before the
+// buffer is touched again.
+struct PinnedBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+  hipError_t reserve(size_t bytes) {
+    if (bytes <= cap) return hipSuccess;
+    if (p) {
+      hipHostFree(p);
+      p = nullptr;
+      cap = 0;
+    }
+    const size_t c = std::max<size_t>(bytes, 4096);
+    hipError_t e = hipHostMalloc(&p, c, hipHostMallocDefault);
+    if (e == hipSuccess) cap = c;
+    return e;
+  }
+  template <typename V>
+  V* as() const {
+    return static_cast<V*>(p);
+  }
+};
+enum { PIN_SUM, PIN_TOTAL, PIN_LIST, PIN_ROOT, PIN_UP, PIN_DEC, PIN_PSTAR, PIN_N };
+static thread_local PinnedBuf tl_pin[PIN_N];
+
 static glu_status jd_sum(const float* E, int64_t n, double* partial, double* sums, hipStream_t st, double* out) {
   const int64_t ntiles = (n + kTilePx - 1) / kTilePx;
   hipLaunchKernelGGL(k_jd_sum_tiles, dim3((unsigned)ntiles), dim3(256), 0, st, E, n, partial);
   hipLaunchKernelGGL(k_jd_sum_final, dim3(1), dim3(256), 0, st, partial, (int)ntiles, sums);
-  hipError_t e = hipMemcpyAsync(out, sums, sizeof(double), hipMemcpyDeviceToHost, st);
+  PinnedBuf& pb = tl_pin[PIN_SUM];
+  hipError_t e = pb.reserve(sizeof(double));
+  if (e == hipSuccess) e = hipMemcpyAsync(pb.p, sums, sizeof(double), hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) return hip_fail(e, "joint: error sum");
+  *out = *pb.as<double>();
   return GLU_OK;
 }
 
@@ -541,19 +631,26 @@ glu_status glu_joint_downsample(const glu_image* I, glu_image* I_low, const glu_
     hipLaunchKernelGGL(k_jd_scan, dim3(1), dim3(256), 0, sm, b.tile_count, (int)ntiles, b.tile_off, b.total);
     hipLaunchKernelGGL(k_jd_scatter, dim3((unsigned)ntiles), dim3(256), 0, sm, b.parent, n, b.tile_off, b.list);
     int total = 0;
-    e = hipMemcpyAsync(&total, b.total, sizeof(int), hipMemcpyDeviceToHost, sm);
+    e = tl_pin[PIN_TOTAL].reserve(sizeof(int));
+    if (e == hipSuccess) e = hipMemcpyAsync(tl_pin[PIN_TOTAL].p, b.total, sizeof(int), hipMemcpyDeviceToHost, sm);
     if (e == hipSuccess) e = hipStreamSynchronize(sm);
     if (e != hipSuccess) return hip_fail(e, "joint: large-error count");
+    total = *tl_pin[PIN_TOTAL].as<int>();
     if (total == 0) break;
     const unsigned lg = (unsigned)((total + 255) / 256);
     hipLaunchKernelGGL(k_jd_union, dim3(lg), dim3(256), 0, sm, b.parent, b.list, b.total, H, W);
     hipLaunchKernelGGL(k_jd_flatten, dim3(lg), dim3(256), 0, sm, b.parent, b.list, b.total, b.list_root);
     list.resize(total);
     root.resize(total);
-    e = hipMemcpyAsync(list.data(), b.list, sizeof(int) * total, hipMemcpyDeviceToHost, sm);
-    if (e == hipSuccess) e = hipMemcpyAsync(root.data(), b.list_root, sizeof(int) * total, hipMemcpyDeviceToHost, sm);
+    e = tl_pin[PIN_LIST].reserve(sizeof(int) * total);
+    if (e == hipSuccess) e = tl_pin[PIN_ROOT].reserve(sizeof(int) * total);
+    if (e == hipSuccess) e = hipMemcpyAsync(tl_pin[PIN_LIST].p, b.list, sizeof(int) * total, hipMemcpyDeviceToHost, sm);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(tl_pin[PIN_ROOT].p, b.list_root, sizeof(int) * total, hipMemcpyDeviceToHost, sm);
     if (e == hipSuccess) e = hipStreamSynchronize(sm);
     if (e != hipSuccess) return hip_fail(e, "joint: component labels");
+    std::memcpy(list.data(), tl_pin[PIN_LIST].p, sizeof(int) * total);
+    std::memcpy(root.data(), tl_pin[PIN_ROOT].p, sizeof(int) * total);
 
     // components in the order of their first pixel (= root, the smallest index)
     std::vector<int> order(total);
@@ -637,10 +734,21 @@ glu_status glu_joint_downsample(const glu_image* I, glu_image* I_low, const glu_
       cm[6] = bbox[4 * c + 1];
       cm[7] = (bbox[4 * c + 2] << 16) | bbox[4 * c + 3];
     }
-    e = hipMemcpyAsync(b.comp, comp.data(), sizeof(int) * comp.size(), hipMemcpyHostToDevice, sm);
-    if (e == hipSuccess) e = hipMemcpyAsync(b.qtab, qtab.data(), sizeof(int) * qtab.size(), hipMemcpyHostToDevice, sm);
-    if (e == hipSuccess) e = hipMemcpyAsync(b.pix, pix.data(), sizeof(int) * pix.size(), hipMemcpyHostToDevice, sm);
-    if (e != hipSuccess) return hip_fail(e, "joint: component table upload");
+    {
+      // one pinned staging buffer holds the three tables back to back
+      const size_t nc = comp.size(), nqt = qtab.size(), npx = pix.size();
+      e = tl_pin[PIN_UP].reserve(sizeof(int) * (nc + nqt + npx));
+      if (e == hipSuccess) {
+        int* up = tl_pin[PIN_UP].as<int>();
+        std::memcpy(up, comp.data(), sizeof(int) * nc);
+        std::memcpy(up + nc, qtab.data(), sizeof(int) * nqt);
+        std::memcpy(up + nc + nqt, pix.data(), sizeof(int) * npx);
+        e = hipMemcpyAsync(b.comp, up, sizeof(int) * nc, hipMemcpyHostToDevice, sm);
+        if (e == hipSuccess) e = hipMemcpyAsync(b.qtab, up + nc, sizeof(int) * nqt, hipMemcpyHostToDevice, sm);
+        if (e == hipSuccess) e = hipMemcpyAsync(b.pix, up + nc + nqt, sizeof(int) * npx, hipMemcpyHostToDevice, sm);
+      }
+      if (e != hipSuccess) return hip_fail(e, "joint: component table upload");
+    }
 
     JdTrialArgs ta{};
     ta.I = static_cast<const float*>(I->data);
@@ -664,17 +772,22 @@ glu_status glu_joint_downsample(const glu_image* I, glu_image* I_low, const glu_
       const int a0 = lvl_start[lv], a1 = lvl_start[lv + 1];
       if (a1 <= a0) continue;
       ta.comp_begin = a0;
-      hipLaunchKernelGGL(k_jd_trial, dim3((unsigned)(a1 - a0)), dim3(256), 0, sm, ta);
+      hipLaunchKernelGGL(p->k == 3 ? k_jd_trial<3> : k_jd_trial<0>, dim3((unsigned)(a1 - a0)), dim3(256), 0, sm, ta);
       e = hipGetLastError();
       if (e != hipSuccess) return hip_fail(e, "joint: trial launch");
     }
     dec.resize(3 * (size_t)M);
     pstar.resize(qtab.size() / 3);
-    e = hipMemcpyAsync(dec.data(), b.dec, sizeof(double) * dec.size(), hipMemcpyDeviceToHost, sm);
+    e = tl_pin[PIN_DEC].reserve(sizeof(double) * dec.size());
+    if (e == hipSuccess) e = tl_pin[PIN_PSTAR].reserve(sizeof(int) * pstar.size());
     if (e == hipSuccess)
-      e = hipMemcpyAsync(pstar.data(), b.pstar, sizeof(int) * pstar.size(), hipMemcpyDeviceToHost, sm);
+      e = hipMemcpyAsync(tl_pin[PIN_DEC].p, b.dec, sizeof(double) * dec.size(), hipMemcpyDeviceToHost, sm);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(tl_pin[PIN_PSTAR].p, b.pstar, sizeof(int) * pstar.size(), hipMemcpyDeviceToHost, sm);
     if (e == hipSuccess) e = hipStreamSynchronize(sm);
     if (e != hipSuccess) return hip_fail(e, "joint: decisions");
+    std::memcpy(dec.data(), tl_pin[PIN_DEC].p, sizeof(double) * dec.size());
+    std::memcpy(pstar.data(), tl_pin[PIN_PSTAR].p, sizeof(int) * pstar.size());
     int accepted = 0;
     for (int c = 0; c < M; ++c) accepted += dec[3 * c] != 0.0;
     if (stats) {
