@@ -2,6 +2,7 @@
 // tile-shape choice shared by every entry point.
 #pragma once
 
+#include <algorithm>
 #include <cstdarg>
 #include <cstdio>
 #include <string>
@@ -18,6 +19,32 @@ void clear_error();
 // Maps a HIP error to GLU_ERR_HIP with context.
 glu_status hip_fail(hipError_t e, const char* what);
 
+// Page-locked host staging (hipHostMalloc) for small copies between the
+// iterations of the joint downsampling calls: copies to or from pageable
+// memory are staged by the runtime and stall the host.  Callers keep one
+// buffer per thread and purpose (thread_local), grown on demand and kept
+// until the process ends; every use ends with a stream synchronisation
+// before the buffer is touched again.
+struct PinnedBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+  hipError_t reserve(size_t bytes) {
+    if (bytes <= cap) return hipSuccess;
+    if (p) {
+      hipHostFree(p);
+      p = nullptr;
+      cap = 0;
+    }
+    const size_t c = std::max<size_t>(bytes, 4096);
+    hipError_t e = hipHostMalloc(&p, c, hipHostMallocDefault);
+    if (e == hipSuccess) cap = c;
+    return e;
+  }
+  template <typename V>
+  V* as() const {
+    return static_cast<V*>(p);
+  }
+};
 inline size_t dtype_size(glu_dtype t) { return t == GLU_F16 ? 2 : 4; }
 inline bool dtype_ok(int t) { return t == GLU_F32 || t == GLU_F16; }
 

@@ -48,48 +48,62 @@ __global__ __launch_bounds__(256) void k_selfgrad(const float* __restrict__ I, i
   for (int c = 0; c < 3; ++c) g[c] = 2.0f * (fmaf(al, La[c] - Lb[c], Lb[c]) - Ip[c]);
 }
 
-// One wave per LR cell: Z = L_q - eta D_q, then the pixel of the cell's
-// block nearest to Z (squared distance, ties to the smallest HR index);
-// L_q becomes that pixel's colour.
+// Eight lanes per LR cell, eight cells per wave: Z = L_q - eta D_q, then
+// the pixel of the cell's block nearest to Z (squared distance, ties to the
+// smallest HR index); L_q becomes that pixel's colour.  A cell's lanes read
+// and write only its own L_q.
+constexpr int kSnapLanes = 8;
+
 __global__ __launch_bounds__(256) void k_snap(const float* __restrict__ I, int64_t I_stride, float* __restrict__ L,
                                               int64_t L_stride, const float* __restrict__ D, float eta, int H, int W,
                                               int h, int w, int s) {
+  // kSnapLanes lanes per LR cell, 64 / kSnapLanes cells per wave
   const int lane = (int)threadIdx.x & 63;
-  const int64_t q = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
-  if (q >= (int64_t)h * w) return;  // uniform over the wave
-  const int qy = (int)(q / w), qx = (int)(q - (int64_t)qy * w);
-  float* Lq = L + (int64_t)qy * L_stride + (int64_t)qx * 3;
-  const float* Dq = D + q * 3;
-  const float z0 = fmaf(-eta, Dq[0], Lq[0]), z1 = fmaf(-eta, Dq[1], Lq[1]), z2 = fmaf(-eta, Dq[2], Lq[2]);
-  const int y0 = qy * s, x0 = qx * s;
-  const int nby = min(H, y0 + s) - y0, nbx = min(W, x0 + s) - x0;
-  const int n = nby * nbx;
+  const int sub = lane % kSnapLanes;
+  const int64_t q = ((int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6)) * (64 / kSnapLanes) +
+                    lane / kSnapLanes;
+  const bool live = q < (int64_t)h * w;
   float best = __builtin_inff();
-  int64_t arg = INT64_MAX;
-  // each lane visits its pixels in raster order of the block, keeping the first minimum
-  for (int j = lane; j < n; j += 64) {
-    const int by = j / nbx, bx = j - by * nbx;
-    const float* p = I + (int64_t)(y0 + by) * I_stride + (int64_t)(x0 + bx) * 3;
-    const float d0 = p[0] - z0, d1 = p[1] - z1, d2 = p[2] - z2;
-    const float dd = fmaf(d2, d2, fmaf(d1, d1, d0 * d0));
-    if (dd < best) {
-      best = dd;
-      arg = (int64_t)(y0 + by) * W + (x0 + bx);
+  int arg = INT32_MAX;  // raster index inside the block
+  int qy = 0, qx = 0, nbx = 1;
+  if (live) {
+    qy = (int)(q / w);
+    qx = (int)(q - (int64_t)qy * w);
+    const float* Lq = L + (int64_t)qy * L_stride + (int64_t)qx * 3;
+    const float* Dq = D + q * 3;
+    const float z0 = fmaf(-eta, Dq[0], Lq[0]), z1 = fmaf(-eta, Dq[1], Lq[1]), z2 = fmaf(-eta, Dq[2], Lq[2]);
+    const int y0 = qy * s, x0 = qx * s;
+    const int nby = min(H, y0 + s) - y0;
+    nbx = min(W, x0 + s) - x0;
+    const int n = nby * nbx;
+    // each lane visits its pixels in raster order of the block, keeping the first minimum
+    for (int j = sub; j < n; j += kSnapLanes) {
+      const int by = j / nbx, bx = j - by * nbx;
+      const float* p = I + (int64_t)(y0 + by) * I_stride + (int64_t)(x0 + bx) * 3;
+      const float d0 = p[0] - z0, d1 = p[1] - z1, d2 = p[2] - z2;
+      const float dd = fmaf(d2, d2, fmaf(d1, d1, d0 * d0));
+      if (dd < best) {
+        best = dd;
+        arg = j;
+      }
     }
   }
-  // lexicographic (distance, HR index) minimum over the wave, fixed order
+  // lexicographic (distance, raster index) minimum over the cell's lanes, in
+  // a fixed order; the raster index inside the block orders the pixels as
+  // their HR indices do
 #pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) {
+  for (int m = kSnapLanes / 2; m >= 1; m >>= 1) {
     const float ob = __shfl_xor(best, m, 64);
-    const int64_t oa = __shfl_xor(arg, m, 64);
+    const int oa = __shfl_xor(arg, m, 64);
     if (ob < best || (ob == best && oa < arg)) {
       best = ob;
       arg = oa;
     }
   }
-  if (lane == 0) {
-    const int py = (int)(arg / W), px = (int)(arg - (int64_t)py * W);
+  if (live && sub == 0) {
+    const int py = qy * s + arg / nbx, px = qx * s + arg % nbx;
     const float* p = I + (int64_t)py * I_stride + (int64_t)px * 3;
+    float* Lq = L + (int64_t)qy * L_stride + (int64_t)qx * 3;
     Lq[0] = p[0];
     Lq[1] = p[1];
     Lq[2] = p[2];
@@ -99,7 +113,8 @@ __global__ __launch_bounds__(256) void k_snap(const float* __restrict__ I, int64
 // Sum of E over the image in a fixed order: kernel 1 sums rows
 // [blockIdx.x * rows, ...) per workgroup (per-thread strided partial sums in
 // double, then a fixed tree in LDS); kernel 2 sums the partials in order.
-constexpr int kSumRows = 16;
+// One row per workgroup keeps a few thousand workgroups in flight.
+constexpr int kSumRows = 1;
 
 __global__ __launch_bounds__(256) void k_esum_part(const float* __restrict__ E, int64_t stride, int H, int W,
                                                    double* __restrict__ part) {
@@ -131,6 +146,8 @@ __global__ __launch_bounds__(256) void k_esum_final(const double* __restrict__ p
 }
 
 static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+static thread_local PinnedBuf tl_sum_pin;
 
 // Workspace layout (256-byte aligned pieces).
 struct JdgLayout {
@@ -220,9 +237,12 @@ glu_status glu_joint_downsample_grad(const glu_image* I, glu_image* I_low, const
   auto esum = [&](double& out) -> glu_status {
     hipLaunchKernelGGL(k_esum_part, dim3((unsigned)nparts), dim3(256), 0, sm, E, theta->row_stride, H, W, part);
     hipLaunchKernelGGL(k_esum_final, dim3(1), dim3(256), 0, sm, part, nparts, dsum);
-    hipError_t e = hipMemcpyAsync(&out, dsum, sizeof(double), hipMemcpyDeviceToHost, sm);
+    PinnedBuf& pb = tl_sum_pin;
+    hipError_t e = pb.reserve(sizeof(double));
+    if (e == hipSuccess) e = hipMemcpyAsync(pb.p, dsum, sizeof(double), hipMemcpyDeviceToHost, sm);
     if (e == hipSuccess) e = hipStreamSynchronize(sm);
     if (e != hipSuccess) return hip_fail(e, "error sum");
+    out = *pb.as<double>();
     return GLU_OK;
   };
   auto copy_L = [&](float* dst, int64_t dst_stride, const float* src, int64_t src_stride) -> glu_status {
@@ -248,7 +268,7 @@ glu_status glu_joint_downsample_grad(const glu_image* I, glu_image* I_low, const
     if ((st = glu_apply_backward(theta, I_low, p, &Gimg, &Dimg, nullptr, ws + lay.S, ws_bytes - lay.S, stream)))
       return st;
     const int64_t cells = (int64_t)h * w;
-    hipLaunchKernelGGL(k_snap, dim3((unsigned)((cells + 3) / 4)), dim3(256), 0, sm,
+    hipLaunchKernelGGL(k_snap, dim3((unsigned)((cells + 4 * (64 / kSnapLanes) - 1) / (4 * (64 / kSnapLanes)))), dim3(256), 0, sm,
                        static_cast<const float*>(I->data), I->row_stride, L, Ls, D, eta, H, W, h, w, p->s);
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "snap launch");

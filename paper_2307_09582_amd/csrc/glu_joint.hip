@@ -495,31 +495,6 @@ static JdLayout jd_layout(int64_t H, int64_t W, int s) {
   return L;
 }
 
-// Page-locked host staging (hipHostMalloc) for the small per-round copies:
-// copies to or from pageable memory are staged by the runtime and stall the
-// host.  One buffer per thread and purpose, grown on demand and kept until
-// the process ends; every use ends with a stream synchronisation before the
-// buffer is touched again.
-struct PinnedBuf {
-  void* p = nullptr;
-  size_t cap = 0;
-  hipError_t reserve(size_t bytes) {
-    if (bytes <= cap) return hipSuccess;
-    if (p) {
-      hipHostFree(p);
-      p = nullptr;
-      cap = 0;
-    }
-    const size_t c = std::max<size_t>(bytes, 4096);
-    hipError_t e = hipHostMalloc(&p, c, hipHostMallocDefault);
-    if (e == hipSuccess) cap = c;
-    return e;
-  }
-  template <typename V>
-  V* as() const {
-    return static_cast<V*>(p);
-  }
-};
 enum { PIN_SUM, PIN_TOTAL, PIN_LIST, PIN_ROOT, PIN_UP, PIN_DEC, PIN_PSTAR, PIN_N };
 static thread_local PinnedBuf tl_pin[PIN_N];
 
