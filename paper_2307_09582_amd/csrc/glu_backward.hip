@@ -52,6 +52,10 @@ struct BwdArgs {
   int32_t groups_x;     // workgroups per LR row
   uint32_t s_magic;     // floor(2^32 / s) for udiv_rt
   uint32_t vec;         // VEC_THETA | VEC_G | VEC_T(dalpha rows)
+  // self-upsampling gradient (register form only): G holds the HR guide I
+  // and T the LR guide, and each pixel's gradient is formed in the kernel as
+  // 2 (alpha T[a] + (1 - alpha) T[b] - I)
+  int32_t self_grad;
   // element offsets between the images of a batch (blockIdx.y)
   int64_t b_th, b_T, b_G, b_da, b_S, b_dT;
 };
@@ -394,7 +398,7 @@ __global__ __launch_bounds__(kThreads) void k_bwd_reg(const BwdArgs a0) {
     sDec[c] = make_uint2((uint32_t)((oa / KW) * lx + oa % KW) | ((uint32_t)((ob / KW) * lx + ob % KW) << 16),
                          (uint32_t)oa | ((uint32_t)ob << 16));
   }
-  if (a.dalpha) {
+  if (a.dalpha || a.self_grad) {
     // rows qy - R .. qy + R, columns qx0 - R .. qx0 + nb - 1 + R, clamped to
     // the LR image (codes from the search never leave it)
     for (int i = tid; i < KW * lx; i += kThreads) {
@@ -457,6 +461,16 @@ __global__ __launch_bounds__(kThreads) void k_bwd_reg(const BwdArgs a0) {
       for (int q = 0; q < P; ++q) {
         const uint2 e = sDec[min(cd[q], K2 * K2 - 1)];
         da[q] = 0.f;
+        if (a.self_grad) {
+          // G = 2 (alpha T[a] + (1 - alpha) T[b] - I); zero past the image
+          const float4 Ta = sT[cl + (e.x & 0xffff)];
+          const float4 Tb = sT[cl + (e.x >> 16)];
+          const float ta[4] = {Ta.x, Ta.y, Ta.z, Ta.w}, tb[4] = {Tb.x, Tb.y, Tb.z, Tb.w};
+          const bool ok = full || (x + q < a.W);
+#pragma unroll
+          for (int ch = 0; ch < C; ++ch)
+            g[q][ch] = ok ? 2.0f * (fmaf(al[q], ta[ch] - tb[ch], tb[ch]) - g[q][ch]) : 0.0f;
+        }
         if (a.dalpha) {
           const float4 Ta = sT[cl + (e.x & 0xffff)];
           const float4 Tb = sT[cl + (e.x >> 16)];
@@ -643,7 +657,7 @@ size_t glu_apply_backward_batched_workspace(int32_t n, int32_t H, int32_t W, int
 static glu_status backward_batched(int32_t n, const glu_batch_strides* bs, const glu_theta* theta,
                                    const glu_image* T_low, const glu_params* p, const glu_image* grad_T_hat,
                                    glu_image* grad_T_low, float* grad_alpha, void* workspace, size_t ws_bytes,
-                                   void* stream) {
+                                   void* stream, bool self_grad = false) {
   glu_status st;
   if ((st = check_batch(n, bs, true))) return st;
   if ((st = check_params(p))) return st;
@@ -703,6 +717,9 @@ static glu_status backward_batched(int32_t n, const glu_batch_strides* bs, const
   }
   int regP = 0;
   const bool reg = reg_geometry(p->s, p->k, C, regP);
+  if (self_grad && (!reg || C != 3 || grad_alpha))
+    return fail(GLU_ERR_UNSUPPORTED, "self-upsampling gradient needs the register form, 3 channels and no dalpha");
+  a.self_grad = self_grad ? 1 : 0;
   if (reg)
     a.nb = reg_geom(p->s, regP, p->k).nb;
   else
@@ -759,3 +776,13 @@ glu_status glu_apply_backward_batched(int32_t n, const glu_batch_strides* stride
 }
 
 }  // extern "C"
+
+namespace glu {
+
+glu_status apply_backward_selfgrad(const glu_theta* theta, const glu_image* I_low, const glu_params* p,
+                                   const glu_image* I, glu_image* grad_I_low, void* workspace, size_t ws_bytes,
+                                   void* stream) {
+  return backward_batched(1, nullptr, theta, I_low, p, I, grad_I_low, nullptr, workspace, ws_bytes, stream, true);
+}
+
+}  // namespace glu

@@ -45,6 +45,15 @@ struct PinnedBuf {
     return static_cast<V*>(p);
   }
 };
+// The backward of Eq. 1 with T_low = I_low for the self-upsampling loss
+// sum_p ||I_hat_p - I_p||^2: grad_I_low of that loss with Theta fixed, with
+// the per-pixel gradient 2 (I_hat - I) formed inside the backward's first
+// pass.  GLU_ERR_UNSUPPORTED for shapes outside its register form; the
+// caller then forms the gradient image itself.
+glu_status apply_backward_selfgrad(const glu_theta* theta, const glu_image* I_low, const glu_params* p,
+                                   const glu_image* I, glu_image* grad_I_low, void* workspace, size_t ws_bytes,
+                                   void* stream);
+
 inline size_t dtype_size(glu_dtype t) { return t == GLU_F16 ? 2 : 4; }
 inline bool dtype_ok(int t) { return t == GLU_F32 || t == GLU_F16; }
 

@@ -258,15 +258,30 @@ glu_status glu_joint_downsample_grad(const glu_image* I, glu_image* I_low, const
   if (err_sums) err_sums[0] = best;
   int best_t = 0;
   if (keep_best && n_steps > 0 && (st = copy_L(Lbest, (int64_t)w * 3, L, Ls))) return st;
+  bool fused_grad = true;
   for (int t = 1; t <= n_steps; ++t) {
-    const int64_t npx = (int64_t)H * W;
-    hipLaunchKernelGGL(k_selfgrad, dim3((unsigned)((npx + 255) / 256)), dim3(256), 0, sm,
-                       static_cast<const float*>(I->data), I->row_stride, static_cast<const float*>(I_low->data), Ls,
-                       theta->code, theta->alpha, theta->row_stride, G, H, W, h, w, p->s, p->k);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return hip_fail(e, "self-gradient launch");
-    if ((st = glu_apply_backward(theta, I_low, p, &Gimg, &Dimg, nullptr, ws + lay.S, ws_bytes - lay.S, stream)))
-      return st;
+    // the backward forms the self-upsampling gradient itself where it can
+    // (register form); otherwise G is written first
+    if (fused_grad) {
+      st = apply_backward_selfgrad(theta, I_low, p, I, &Dimg, ws + lay.S, ws_bytes - lay.S, stream);
+      if (st == GLU_ERR_UNSUPPORTED) {
+        clear_error();
+        fused_grad = false;
+      } else if (st) {
+        return st;
+      }
+    }
+    if (!fused_grad) {
+      const int64_t npx = (int64_t)H * W;
+      hipLaunchKernelGGL(k_selfgrad, dim3((unsigned)((npx + 255) / 256)), dim3(256), 0, sm,
+                         static_cast<const float*>(I->data), I->row_stride, static_cast<const float*>(I_low->data), Ls,
+                         theta->code, theta->alpha, theta->row_stride, G, H, W, h, w, p->s, p->k);
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return hip_fail(e, "self-gradient launch");
+      if ((st = glu_apply_backward(theta, I_low, p, &Gimg, &Dimg, nullptr, ws + lay.S, ws_bytes - lay.S, stream)))
+        return st;
+    }
+    hipError_t e;
     const int64_t cells = (int64_t)h * w;
     hipLaunchKernelGGL(k_snap, dim3((unsigned)((cells + 4 * (64 / kSnapLanes) - 1) / (4 * (64 / kSnapLanes)))), dim3(256), 0, sm,
                        static_cast<const float*>(I->data), I->row_stride, L, Ls, D, eta, H, W, h, w, p->s);
