@@ -52,10 +52,6 @@ struct BwdArgs {
   int32_t groups_x;     // workgroups per LR row
   uint32_t s_magic;     // floor(2^32 / s) for udiv_rt
   uint32_t vec;         // VEC_THETA | VEC_G | VEC_T(dalpha rows)
-  // self-upsampling gradient (register form only): G holds the HR guide I
-  // and T the LR guide, and each pixel's gradient is formed in the kernel as
-  // 2 (alpha T[a] + (1 - alpha) T[b] - I)
-  int32_t self_grad;
   // element offsets between the images of a batch (blockIdx.y)
   int64_t b_th, b_T, b_G, b_da, b_S, b_dT;
 };
@@ -372,7 +368,10 @@ __host__ __device__ inline int reg_lds_words(const RegGeom& g, int k, int C) {
   return k * (g.nb + k - 1) + (K2 * K2 * 2 + 3) / 4 + (g.rw > 1 ? (g.rw * g.nb * K2 * C + 3) / 4 : 0);
 }
 
-template <typename T, int C, int P, int KW>
+// SELF: self-upsampling gradient.  G then holds the HR guide I and T the LR
+// guide, and each pixel's gradient is formed here as
+// 2 (alpha T[a] + (1 - alpha) T[b] - I).
+template <typename T, int C, int P, int KW, bool SELF = false>
 __global__ __launch_bounds__(kThreads) void k_bwd_reg(const BwdArgs a0) {
   extern __shared__ float4 smem[];
   constexpr int K2 = KW * KW, R = KW / 2;
@@ -398,7 +397,7 @@ __global__ __launch_bounds__(kThreads) void k_bwd_reg(const BwdArgs a0) {
     sDec[c] = make_uint2((uint32_t)((oa / KW) * lx + oa % KW) | ((uint32_t)((ob / KW) * lx + ob % KW) << 16),
                          (uint32_t)oa | ((uint32_t)ob << 16));
   }
-  if (a.dalpha || a.self_grad) {
+  if (a.dalpha || SELF) {
     // rows qy - R .. qy + R, columns qx0 - R .. qx0 + nb - 1 + R, clamped to
     // the LR image (codes from the search never leave it)
     for (int i = tid; i < KW * lx; i += kThreads) {
@@ -461,7 +460,7 @@ __global__ __launch_bounds__(kThreads) void k_bwd_reg(const BwdArgs a0) {
       for (int q = 0; q < P; ++q) {
         const uint2 e = sDec[min(cd[q], K2 * K2 - 1)];
         da[q] = 0.f;
-        if (a.self_grad) {
+        if constexpr (SELF) {
           // G = 2 (alpha T[a] + (1 - alpha) T[b] - I); zero past the image
           const float4 Ta = sT[cl + (e.x & 0xffff)];
           const float4 Tb = sT[cl + (e.x >> 16)];
@@ -573,7 +572,14 @@ static BwdKernel pick_reg_p(bool f16, int C) {
   }
 }
 
-static BwdKernel pick_reg(bool f16, int C, int P, int k) {
+static BwdKernel pick_reg(bool f16, int C, int P, int k, bool self_grad) {
+  if (self_grad) {
+    // float32 guides with 3 channels only
+    if (k == 5) return k_bwd_reg<float, 3, 4, 5, true>;
+    if (P == 4) return k_bwd_reg<float, 3, 4, 3, true>;
+    if (P == 3) return k_bwd_reg<float, 3, 3, 3, true>;
+    return k_bwd_reg<float, 3, 2, 3, true>;
+  }
   if (k == 5) return pick_reg_p<4, 5>(f16, C);
   if (P == 4) return pick_reg_p<4, 3>(f16, C);
   if (P == 3) return pick_reg_p<3, 3>(f16, C);
@@ -717,9 +723,9 @@ static glu_status backward_batched(int32_t n, const glu_batch_strides* bs, const
   }
   int regP = 0;
   const bool reg = reg_geometry(p->s, p->k, C, regP);
-  if (self_grad && (!reg || C != 3 || grad_alpha))
-    return fail(GLU_ERR_UNSUPPORTED, "self-upsampling gradient needs the register form, 3 channels and no dalpha");
-  a.self_grad = self_grad ? 1 : 0;
+  if (self_grad && (!reg || C != 3 || grad_alpha || T_low->dtype != GLU_F32))
+    return fail(GLU_ERR_UNSUPPORTED,
+                "self-upsampling gradient needs the register form, a 3-channel float32 guide and no dalpha");
   if (reg)
     a.nb = reg_geom(p->s, regP, p->k).nb;
   else
@@ -744,7 +750,7 @@ static glu_status backward_batched(int32_t n, const glu_batch_strides* bs, const
   const int64_t groups = (int64_t)h * a.groups_x;
   if (groups > 0x7fffffff) return fail(GLU_ERR_UNSUPPORTED, "image too large");
   hipStream_t sm = (hipStream_t)stream;
-  BwdKernel kern = reg ? pick_reg(T_low->dtype == GLU_F16, C, regP, p->k) : pick_bwd(T_low->dtype == GLU_F16, P, p->k, C);
+  BwdKernel kern = reg ? pick_reg(T_low->dtype == GLU_F16, C, regP, p->k, self_grad) : pick_bwd(T_low->dtype == GLU_F16, P, p->k, C);
   hipLaunchKernelGGL(kern, dim3((unsigned)groups, (unsigned)n), dim3(kThreads), lds, sm, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "backward pass 1 launch");
