@@ -157,3 +157,17 @@ def test_joint_2048_x8_five_rounds():
     stats, log, rp = _check(glu, I, L0, 8, 3, "exhaustive", O.TAU, 5, check_all_pixels=False)
     print(stats, "replays", rp.replays)
     assert stats["err_sum_final"] <= stats["err_sum_initial"]
+
+
+def test_giant_component_box_walk():
+    """One component covering the whole image (tau = 0 on noise): its 16384
+    affected LR cells exceed the trial's LDS list, so the trial walks the
+    component's bounding box instead; decisions, I_low and Theta as the
+    oracle's."""
+    glu = _glu()
+    log_case(test="joint_giant_component")
+    rng = np.random.default_rng(17)
+    I = rng.uniform(0, 1, (256, 256, 3)).astype(np.float32)
+    L0 = O.downsample_point(I, 2)
+    stats, log, _ = _check(glu, I, L0, 2, 3, "exhaustive", 0.0, 1)
+    assert stats["n_components"][0] == 1 and len(log) == 1
