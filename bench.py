@@ -66,6 +66,8 @@ def _parse():
     ap.add_argument("--only", choices=["all", "step"], default="all",
                     help="'step' times only the headline step (for profiling)")
     ap.add_argument("--no-configs", action="store_true", help="skip the further workloads")
+    ap.add_argument("--config-only", choices=["plain_512_box4", "joint_2048_x8_5rounds"], default=None,
+                    help="run only this one of the further workloads (for a profile of it)")
     ap.add_argument("--kernel-modes", default="exhaustive,fast,gnu",
                     help="search modes of the per-kernel timings (fast and gnu share the fast kernels, so a "
                          "kernel trace that should tell them apart times one of them)")
@@ -295,8 +297,8 @@ def main():
         }
 
     configs = None
-    if args.only == "all" and not args.no_configs:
-        configs = _configs(np, torch, synth, glu, dev, stream, scene)
+    if (args.only == "all" or args.config_only) and not args.no_configs:
+        configs = _configs(np, torch, synth, glu, dev, stream, scene, args.config_only)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -357,11 +359,25 @@ def main():
     print(json.dumps(res), flush=True)
 
 
-def _configs(np, torch, synth, glu, dev, stream, scene):
-    """The further workloads, each timed with HIP events on `stream`."""
+def _configs(np, torch, synth, glu, dev, stream, scene, only=None):
+    """The further workloads, each timed with HIP events on `stream`; `only`
+    names the single workload to run."""
     out = {}
 
     # plain GLU, 512 x 512, box x4 to 128 x 128 (cache-resident)
+    if only in (None, "plain_512_box4"):
+        _plain_512(np, torch, synth, glu, dev, stream, out)
+    if only == "plain_512_box4":
+        return out
+    if only not in (None, "joint_2048_x8_5rounds"):
+        return out
+    _joint_2048(np, torch, synth, glu, dev, stream, out)
+    if only == "joint_2048_x8_5rounds":
+        return out
+    return _configs_rest(np, torch, synth, glu, dev, stream, scene, out)
+
+
+def _plain_512(np, torch, synth, glu, dev, stream, out):
     I = torch.from_numpy(synth.voronoi(512, 512, n_cells=64, n_dots=20, dot_px=(2, 4), seed=1)).to(dev)
     Il = glu.downsample(I, 4, "box")
     T = _lr_f1_torch(torch, Il).contiguous()
@@ -374,6 +390,8 @@ def _configs(np, torch, synth, glu, dev, stream, scene):
     out["plain_512_box4"] = r
     print("plain 512 done", file=sys.stderr, flush=True)
 
+
+def _joint_2048(np, torch, synth, glu, dev, stream, out):
     # joint downsampling, 2048 x 2048 x8, 5 rounds (Algorithm 2)
     I = torch.from_numpy(synth.voronoi(2048, 2048, n_cells=512, n_dots=200, dot_px=(1, 3), seed=2)).to(dev)
     L0 = glu.downsample(I, 8, "point")
@@ -418,8 +436,9 @@ def _configs(np, torch, synth, glu, dev, stream, scene):
                                 "err_sums": [round(v, 3) for v in sums], "best_step": best}
     out["joint_2048_x8_5rounds"] = r
     print("joint done", file=sys.stderr, flush=True)
-    del I, L0
 
+
+def _configs_rest(np, torch, synth, glu, dev, stream, scene, out):
     # 60 frames of 3840 x 2160, float16 storage, one persistent launch under
     # a captured graph; frame t is the scene crop at column 3 t
     canvas = torch.from_numpy(scene.canvas.astype(np.float32)).to(dev)
