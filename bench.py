@@ -172,8 +172,8 @@ def main():
     args = _parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: the GLU hot path of this build runs on a single MI355X "
-              "(multi-GPU sharding is a design note only); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: this GLU library runs on a single MI355X and does not shard "
+              "across GPUs; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
