@@ -91,7 +91,7 @@ int n_tile_variants() { return (int)(sizeof(kVariantCols) / sizeof(kVariantCols[
 TileChoice choose_tile(int s, int k, int mode, bool fused, bool table, int variant) {
   if (variant < 0 || variant >= n_tile_variants()) variant = 0;
   TileChoice tc;
-  tc.P = strip_pixels(s);
+  tc.P = search_strip_pixels(s, k, mode == MODE_EXH);
   const int cols = kVariantCols[variant];
   tc.tqx = std::max(1, cols / s);
   // the fast search keeps less per-strip state: its default tile gives each
@@ -124,8 +124,8 @@ void fill_tiles(ImgDesc& d, const TileChoice& tc) {
 static int kw_class(int k) { return k == 3 ? 0 : (k == 5 ? 1 : 2); }
 
 int kernel_variant(int k, int P, int mode, int dtype, bool table) {
-  const int pidx = P - 1;
-  return (((kw_class(k) * 4 + pidx) * 2 + mode) * 2 + dtype) * 2 + (table ? 1 : 0);
+  const int pidx = P - 1;  // P = 1 .. 8
+  return (((kw_class(k) * 8 + pidx) * 2 + mode) * 2 + dtype) * 2 + (table ? 1 : 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -188,6 +188,9 @@ static SearchKernel pick_search_p(int mode, int dtype, bool fused, bool table) {
 template <int KW>
 static SearchKernel pick_search_k(int P, int mode, int dtype, bool fused, bool table) {
   if (P == 4) return pick_search_p<KW, 4>(mode, dtype, fused, table);
+  if constexpr (KW == 5) {
+    if (P == 8) return pick_search_p<KW, 8>(mode, dtype, fused, table);
+  }
   if (P == 3) return pick_search_p<KW, 3>(mode, dtype, fused, table);
   if (P == 2) return pick_search_p<KW, 2>(mode, dtype, fused, table);
   return pick_search_p<KW, 1>(mode, dtype, fused, table);

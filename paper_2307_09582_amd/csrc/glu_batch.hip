@@ -109,6 +109,9 @@ typedef void (*BatchKernel)(const BatchTable);
 template <int MODE, int KW, bool TABLE>
 static BatchKernel pick_batch_kwt(int P, int dtype) {
   if (P == 4) return dtype == GLU_F16 ? k_batch<MODE, KW, 4, __half, TABLE> : k_batch<MODE, KW, 4, float, TABLE>;
+  if constexpr (KW == 5) {
+    if (P == 8) return dtype == GLU_F16 ? k_batch<MODE, KW, 8, __half, TABLE> : k_batch<MODE, KW, 8, float, TABLE>;
+  }
   if (P == 3) return dtype == GLU_F16 ? k_batch<MODE, KW, 3, __half, TABLE> : k_batch<MODE, KW, 3, float, TABLE>;
   if (P == 2) return dtype == GLU_F16 ? k_batch<MODE, KW, 2, __half, TABLE> : k_batch<MODE, KW, 2, float, TABLE>;
   return dtype == GLU_F16 ? k_batch<MODE, KW, 1, __half, TABLE> : k_batch<MODE, KW, 1, float, TABLE>;
@@ -252,7 +255,8 @@ static glu_status plan_build(const glu_batch_item* items, int32_t n, const glu_p
     ImgDesc d = all[order[j]];
     if (groups.empty() || host.back().variant != d.variant) {
       BatchGroup g{};
-      g.kern = pick_batch(mode, d.k, strip_pixels(d.s), d.dtype, uses_pair_table(mode, d.k, d.s));
+      g.kern = pick_batch(mode, d.k, search_strip_pixels(d.s, d.k, mode == MODE_EXH), d.dtype,
+                          uses_pair_table(mode, d.k, d.s));
       g.first = (int32_t)host.size();
       g.lds = 16;
       groups.push_back(g);

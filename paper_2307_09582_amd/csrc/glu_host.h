@@ -77,6 +77,14 @@ struct TileChoice {
 // centre, so P divides s (4, else 3, else 2, else 1).
 inline int strip_pixels(int s) { return s % 4 == 0 ? 4 : (s % 3 == 0 ? 3 : (s % 2 == 0 ? 2 : 1)); }
 
+// Pixels per strip of a search launch: the exhaustive 5 x 5 search builds
+// the constants of its 300 pairs per strip, so it shares them over 8 pixels
+// when 8 divides s (strips of 8 did not pay for 7 x 7 windows, whose
+// runtime-k kernel loses more to register pressure).
+inline int search_strip_pixels(int s, int k, bool exhaustive) {
+  return (exhaustive && k == 5 && s % 8 == 0) ? 8 : strip_pixels(s);
+}
+
 // Default tile: about 64 HR columns by enough rows for 256 strips, shrunk
 // until the LDS of the tile fits.  `variant` selects alternatives for the
 // autotuner (0 = default).

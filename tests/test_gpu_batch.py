@@ -43,6 +43,7 @@ SPECS = [
     (260, 300, 4, 3, 3, "f32"),
     (90, 110, 6, 3, 3, "f32"),
     (52, 70, 10, 5, 2, "f16"),
+    (64, 96, 8, 5, 3, "f32"),
 ]
 
 

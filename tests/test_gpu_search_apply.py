@@ -110,6 +110,9 @@ CASES = [
     (80, 100, 9, 3, 3, "exhaustive", "f32"),
     (80, 100, 9, 3, 3, "fast", "f16"),
     (33, 47, 3, 5, 3, "exhaustive", "f32"),
+    (72, 88, 8, 5, 3, "exhaustive", "f32"),
+    (96, 112, 16, 5, 2, "exhaustive", "f16"),
+    (41, 67, 8, 5, 1, "exhaustive", "f32"),
 ]
 
 
