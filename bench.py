@@ -488,7 +488,7 @@ def _configs_rest(np, torch, synth, glu, dev, stream, scene, out):
         for mode in ("exhaustive", "fast"):
             n = 20 if kk <= 5 else 3
             ms = _events_ms(torch, stream,
-                            lambda i: glu.search_apply(I, Il8, T8, 8, kk, EPS, mode, theta=thw, out=ow), n, 3)
+                            lambda i: glu.search_apply(I, Il8, T8, 8, kk, EPS, mode, theta=thw, out=ow), n, n)
             row[mode] = {"us": round(1e3 * ms, 1), "Mpx_s": round(H * W / (ms * 1e-3) / 1e6, 1)}
         sweep["k_at_s8"][str(kk)] = row
     for ss in (2, 3, 4, 6, 8, 16, 32, 64, 128):
