@@ -121,7 +121,8 @@ void fill_tiles(ImgDesc& d, const TileChoice& tc) {
   d.tiles_y = ceil_div(d.h, tc.tqy);
 }
 
-static int kw_class(int k) { return k == 3 ? 0 : (k == 5 ? 1 : 2); }
+// window classes with their own kernels: 3, 5 and 7 are compile-time sizes, others run-time
+static int kw_class(int k) { return k == 3 ? 0 : (k == 5 ? 1 : (k == 7 ? 3 : 2)); }
 
 int kernel_variant(int k, int P, int mode, int dtype, bool table) {
   const int pidx = P - 1;  // P = 1 .. 8
@@ -199,6 +200,7 @@ static SearchKernel pick_search_k(int P, int mode, int dtype, bool fused, bool t
 static SearchKernel pick_search(int k, int P, int mode, int dtype, bool fused, bool table) {
   if (k == 3) return pick_search_k<3>(P, mode, dtype, fused, table);
   if (k == 5) return pick_search_k<5>(P, mode, dtype, fused, table);
+  if (k == 7) return pick_search_k<7>(P, mode, dtype, fused, table);
   return pick_search_k<0>(P, mode, dtype, fused, table);
 }
 

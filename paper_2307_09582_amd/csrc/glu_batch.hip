@@ -129,6 +129,7 @@ template <int MODE>
 static BatchKernel pick_batch_m(int k, int P, int dtype, bool table) {
   if (k == 3) return pick_batch_kw<MODE, 3>(P, dtype, table);
   if (k == 5) return pick_batch_kw<MODE, 5>(P, dtype, table);
+  if (k == 7) return pick_batch_kw<MODE, 7>(P, dtype, table);
   return pick_batch_kw<MODE, 0>(P, dtype, table);
 }
 
