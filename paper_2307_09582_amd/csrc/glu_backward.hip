@@ -481,9 +481,13 @@ __global__ __launch_bounds__(kThreads) void k_bwd_reg(const BwdArgs a0) {
         }
         if (a.S) {
           const int oa = (int)(e.y & 0xffff), ob = (int)(e.y >> 16);
+          // o_a and o_b differ except in a (j, j) code, where the one weight
+          // is alpha + (1 - alpha), summed in float like the two terms
+          const float wb = 1.0f - al[q];
+          const float wa = oa == ob ? al[q] + wb : al[q];
 #pragma unroll
           for (int o = 0; o < K2; ++o) {
-            const float wt = (oa == o ? al[q] : 0.0f) + (ob == o ? 1.0f - al[q] : 0.0f);
+            const float wt = oa == o ? wa : (ob == o ? wb : 0.0f);
 #pragma unroll
             for (int ch = 0; ch < C; ++ch) acc[o][ch] = fmaf(wt, g[q][ch], acc[o][ch]);
           }

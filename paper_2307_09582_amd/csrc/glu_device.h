@@ -493,16 +493,20 @@ __device__ __forceinline__ void fast_strip(const float (&ip)[P][3], const Win& w
     }
     return;
   }
-  float La[P][3], sa[P], omb[P];
+  // sae: the anchor's distance plus eps, the part of the Eq. 5 denominator
+  // fixed for the pixel; bsel: window offset of the best partner so far
+  // (the code is formed once, after the loop)
+  float La[P][3], sae[P], omb[P];
+  int bsel[P];
 #pragma unroll
   for (int q = 0; q < P; ++q) {
     const float4 A = win(ia[q]);
     La[q][0] = A.x;
     La[q][1] = A.y;
     La[q][2] = A.z;
-    sa[q] = __builtin_amdgcn_sqrtf(dmin[q]);
+    sae[q] = __builtin_amdgcn_sqrtf(dmin[q]) + eps;
     best[q] = dmin[q];
-    code[q] = ia[q] * K2 + ia[q];
+    bsel[q] = ia[q];
     omb[q] = 1.0f;
   }
 #pragma unroll kUnrollJ
@@ -518,7 +522,7 @@ __device__ __forceinline__ void fast_strip(const float (&ip)[P][3], const Win& w
         const float dx = ip[q][0] - Lb.x, dy = ip[q][1] - Lb.y, dz = ip[q][2] - Lb.z;
         sb = __builtin_amdgcn_sqrtf(fmaf(dz, dz, fmaf(dy, dy, dx * dx)));
       }
-      const float den = (sa[q] + sb) + eps;
+      const float den = sae[q] + sb;
       const float om = sb * __builtin_amdgcn_rcpf(den);
       const float om1 = 1.0f - om;
       // residual = om L_a + (1 - om) L_b - I, negated
@@ -531,14 +535,14 @@ __device__ __forceinline__ void fast_strip(const float (&ip)[P][3], const Win& w
       const float e2 = fmaf(rz, rz, fmaf(ry, ry, rx * rx));
       const bool lt = e2 < best[q];
       best[q] = lt ? e2 : best[q];
-      code[q] = lt ? ia[q] * K2 + b : code[q];
+      bsel[q] = lt ? b : bsel[q];
       omb[q] = lt ? om : omb[q];
     }
   }
 #pragma unroll
   for (int q = 0; q < P; ++q) {
-    const int ob = code[q] - ia[q] * K2;
-    alpha[q] = (ob == ia[q]) ? 1.0f : omb[q];
+    code[q] = ia[q] * K2 + bsel[q];
+    alpha[q] = (bsel[q] == ia[q]) ? 1.0f : omb[q];
   }
 }
 
