@@ -498,7 +498,7 @@ def test_joint_literal_reading_runs():
 
 
 # ---------------------------------------------------------------------------
-# Pair evaluators used to judge another implementation's choice
+# Pair evaluators used to check another implementation's choice
 # ---------------------------------------------------------------------------
 def test_pair_evaluators_reproduce_search():
     """Evaluating the search's own winners gives back its weight and error,
