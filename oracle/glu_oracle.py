@@ -6,10 +6,11 @@ links this module: only ``tests/``, ``__graft_entry__.smoke()`` and the
 time a CPU reference.  It shares no code with the HIP path.
 
 Written from the paper (Song et al., "Guided Linear Upsampling", ACM TOG
-42(4), 2023).  Every step follows the paper's definitions in their stated
-order; NumPy arrays run each step over many pixels at once, but no step is
-blocked, fused or reordered.  All arithmetic is float64: inputs that arrive
-as float32 or float16 are upcast exactly.
+42(4), 2023).  Each function computes the paper's definition directly (the
+search, Eq. 1 and its gradient) or, for the heuristic of Alg. 2, takes its
+steps in the paper's order; NumPy arrays run each step over many pixels at
+once, but no step is blocked, fused or reordered.  All arithmetic is
+float64: inputs that arrive as float32 or float16 are upcast exactly.
 
 Notation (Sec. 3.1):
   I      high-resolution guide, H x W x 3
@@ -444,6 +445,78 @@ def _affected_pixels(Q, h, w, H, W, s, k):
     return np.flatnonzero(sel)
 
 
+def _components_in_raster_order(large, H, W):
+    """The 8-connected components of the large-error mask, each as its flat
+    HR indices in ascending order, listed by their first pixel (Alg. 2
+    clusters the large-error set once per iteration)."""
+    labels, M = ccl8(large.reshape(H, W))
+    flat = labels.ravel()
+    members = np.flatnonzero(flat)
+    comps = [[] for _ in range(M)]
+    for p in members:
+        comps[flat[p] - 1].append(int(p))
+    return [np.asarray(c, dtype=np.int64) for c in comps]
+
+
+@dataclass
+class _JointState:
+    """What Alg. 2 updates in place: I_down (flat view Lf of L) and the
+    search result (a, b, alpha, E) of every HR pixel."""
+
+    I: np.ndarray
+    L: np.ndarray
+    Lf: np.ndarray
+    If: np.ndarray
+    a: np.ndarray
+    b: np.ndarray
+    alpha: np.ndarray
+    E: np.ndarray
+    cell_of: np.ndarray  # LR cell under each HR pixel
+
+
+def _component_trial(st, C, n, s, k, eps, mode, reading, decide):
+    """One trial of Alg. 2 for the component C (flat HR indices, ascending).
+
+    Q is the set of LR cells under C.  Every I_down[q] becomes the colour of
+    the pixel of C in q's block with the largest current error (first such
+    in HR order).  The pixels named by the reading (the affected set, whose
+    windows reach Q, or C itself) are searched again; the trial stays when
+    their summed error did not grow, else I_down and their search results
+    are restored.  Returns the Decision."""
+    H, W = st.I.shape[:2]
+    h, w = st.L.shape[:2]
+    Q = np.unique(st.cell_of[C])
+    if reading == "affected":
+        R = _affected_pixels(Q, h, w, H, W, s, k)
+    elif reading == "literal":
+        R = C
+    else:
+        raise ValueError("reading must be 'affected' or 'literal'")
+    saved_L = st.Lf[Q].copy()
+    saved = (st.a[R].copy(), st.b[R].copy(), st.alpha[R].copy(), st.E[R].copy())
+    e0 = float(st.E[R].sum())
+    q_pstar = []
+    for q in Q:
+        members = C[st.cell_of[C] == q]  # ascending HR index
+        Em = st.E[members]
+        pstar = int(members[int(np.argmax(Em))])  # first maximum
+        if decide is not None:
+            pstar = decide("argmax", (int(q), members, Em), pstar)
+        q_pstar.append((int(q), pstar))
+    for q, pstar in q_pstar:
+        st.Lf[q] = st.If[pstar]
+    rs = search(st.I, st.L, s, k, eps, mode, pixels=R)
+    st.a[R], st.b[R], st.alpha[R], st.E[R] = rs.a, rs.b, rs.alpha, rs.err
+    e1 = float(st.E[R].sum())
+    keep = not (e1 > e0)
+    if decide is not None:
+        keep = decide("accept", (e0, e1, R.size), keep)
+    if not keep:
+        st.Lf[Q] = saved_L
+        st.a[R], st.b[R], st.alpha[R], st.E[R] = saved
+    return Decision(n, int(C[0]), keep, e0, e1, q_pstar)
+
+
 def joint_downsample(
     I,
     L0,
@@ -456,83 +529,43 @@ def joint_downsample(
     reading="affected",
     decide=None,
 ) -> JointResult:
-    """Algorithm 2: alternate the pair search with trial replacements of I_down.
+    """Joint optimisation of down- and upsampling (Sec. 3.3, Alg. 2).
 
-    I_down starts at ``L0`` (regular-grid downsampling by default, Alg. 2)
-    and Theta, E at the search on it.  Each of up to ``max_iter`` rounds:
-      1. large-error set {p : E_p > tau}; stop if empty;
-      2. its 8-connected components C_1..C_M (raster order of first pixel);
-      3. for each component in turn: back up I_down, Theta, E; e0 = sum of
-         E over the pixels re-evaluated; for every LR cell q whose block
-         meets C_i set I_down[q] = I[p*], p* the pixel of [q_up] & C_i with
-         the largest E; re-search; e1 = the same sum; roll back if e1 > e0.
-    ``decide`` (optional) is called as decide(kind, payload, default) at each
-    decision so a test can replay another implementation's near-tie
-    decisions; it must return the decision to take.
+    I_down starts at ``L0`` (regular-grid downsampling by default) and
+    Theta, E at the search on it.  Each of up to ``max_iter`` iterations
+    takes the pixels with E > tau (none: stop), clusters them into
+    8-connected components, and runs one trial per component in the order of
+    their first pixels (``_component_trial``), each trial seeing the ones
+    before it.  ``decide`` (optional) is called as decide(kind, payload,
+    default) at each decision so a test can replay another implementation's
+    near-tie decisions; it must return the decision to take.
     """
     I = np.asarray(I, dtype=np.float64)
     H, W = I.shape[:2]
     L = np.array(L0, dtype=np.float64, copy=True)
     h, w = L.shape[:2]
-    Lf = L.reshape(h * w, -1)  # view
-    If = I.reshape(H * W, -1)
     r0 = search(I, L, s, k, eps, mode)
-    a, b, alpha, E = r0.a.copy(), r0.b.copy(), r0.alpha.copy(), r0.err.copy()
-    res = JointResult(L=L, a=a, b=b, alpha=alpha, err=E, err_sum_initial=float(E.sum()))
-    ys_all, xs_all = np.divmod(np.arange(H * W, dtype=np.int64), W)
-    cell_of = (ys_all // s) * w + (xs_all // s)
+    ys, xs = np.divmod(np.arange(H * W, dtype=np.int64), W)
+    st = _JointState(I=I, L=L, Lf=L.reshape(h * w, -1), If=I.reshape(H * W, -1), a=r0.a.copy(), b=r0.b.copy(),
+                     alpha=r0.alpha.copy(), E=r0.err.copy(), cell_of=(ys // s) * w + (xs // s))
+    res = JointResult(L=L, a=st.a, b=st.b, alpha=st.alpha, err=st.E, err_sum_initial=float(st.E.sum()))
     for n in range(1, max_iter + 1):
-        large = E > tau
+        large = st.E > tau
         if decide is not None:
-            large = decide("membership", E, large)
+            large = decide("membership", st.E, large)
         if not large.any():
             break
-        labels, M = ccl8(large.reshape(H, W))
+        comps = _components_in_raster_order(large, H, W)
         res.rounds_run = n
         res.n_large.append(int(large.sum()))
-        res.n_components.append(M)
-        acc_count = 0
-        lab_flat = labels.ravel()
-        order = np.flatnonzero(lab_flat)
-        comp_pixels: list[list[int]] = [[] for _ in range(M + 1)]
-        for p in order:  # raster order inside each component
-            comp_pixels[lab_flat[p]].append(int(p))
-        for ci in range(1, M + 1):
-            C = np.asarray(comp_pixels[ci], dtype=np.int64)
-            Q = np.unique(cell_of[C])
-            if reading == "affected":
-                A = _affected_pixels(Q, h, w, H, W, s, k)
-            elif reading == "literal":
-                A = C
-            else:
-                raise ValueError("reading must be 'affected' or 'literal'")
-            bak_L = Lf[Q].copy()
-            bak = (a[A].copy(), b[A].copy(), alpha[A].copy(), E[A].copy())
-            e0 = float(E[A].sum())
-            q_pstar = []
-            for q in Q:
-                members = C[cell_of[C] == q]  # ascending HR index
-                Em = E[members]
-                pstar = int(members[int(np.argmax(Em))])  # first maximum
-                if decide is not None:
-                    pstar = decide("argmax", (int(q), members, Em), pstar)
-                q_pstar.append((int(q), pstar))
-            for q, pstar in q_pstar:
-                Lf[q] = If[pstar]
-            rs = search(I, L, s, k, eps, mode, pixels=A)
-            a[A], b[A], alpha[A], E[A] = rs.a, rs.b, rs.alpha, rs.err
-            e1 = float(E[A].sum())
-            accept = not (e1 > e0)
-            if decide is not None:
-                accept = decide("accept", (e0, e1, A.size), accept)
-            if not accept:
-                Lf[Q] = bak_L
-                a[A], b[A], alpha[A], E[A] = bak
-            else:
-                acc_count += 1
-            res.log.append(Decision(n, int(C[0]), accept, e0, e1, q_pstar))
-        res.n_accepted.append(acc_count)
-    res.err_sum_final = float(E.sum())
+        res.n_components.append(len(comps))
+        kept = 0
+        for C in comps:
+            d = _component_trial(st, C, n, s, k, eps, mode, reading, decide)
+            kept += int(d.accepted)
+            res.log.append(d)
+        res.n_accepted.append(kept)
+    res.err_sum_final = float(st.E.sum())
     return res
 
 

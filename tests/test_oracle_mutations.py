@@ -41,7 +41,10 @@ MUTATIONS = [
      "return (1.0 - al) * Tf[np.asarray(a)] + al * Tf[np.asarray(b)]"),
     ("backward sends alpha G to b", "np.add.at(dT, b, (1.0 - al)[:, None] * Gf)", "np.add.at(dT, b, al[:, None] * Gf)"),
     ("backward dalpha sign", "Tf[a] - Tf[b])", "Tf[b] - Tf[a])"),
-    ("rollback condition reversed", "accept = not (e1 > e0)", "accept = not (e1 < e0)"),
+    ("rollback condition reversed", "keep = not (e1 > e0)", "keep = not (e1 < e0)"),
+    ("literal reading re-searches the affected set", "        R = C\n",
+     "        R = _affected_pixels(Q, h, w, H, W, s, k)\n"),
+    ("trial error sums over one pixel", "e0 = float(st.E[R].sum())", "e0 = float(st.E[R[:1]].sum())"),
     ("replacement takes the smallest error", "pstar = int(members[int(np.argmax(Em))])",
      "pstar = int(members[int(np.argmin(Em))])"),
     ("4-connected components",
@@ -83,6 +86,7 @@ def _pins():
         lambda: P.test_joint_recovers_missed_dot(),
         lambda: P.test_joint_invariants_on_voronoi(),
         lambda: P.test_joint_constructed_rollback(),
+        lambda: P.test_joint_literal_reading_sums_the_component(),
         lambda: P.test_exact_ties_go_to_the_earliest_candidate(),
         lambda: P.test_joint_replacement_takes_the_largest_error(),
         lambda: P.test_self_upsampling_gradient_finite_differences(),

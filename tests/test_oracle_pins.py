@@ -55,6 +55,21 @@ def _segment_setup(Ip):
     return I, L
 
 
+def test_segment_example_fixture_is_its_closed_form():
+    """The stored worked example is what the committed generator writes from
+    the closed forms of Eq. 4 and Eq. 5 (40-digit decimal arithmetic)."""
+    import decimal
+    import importlib.util
+
+    spec = importlib.util.spec_from_file_location("make_segment_example",
+                                                  os.path.join(GOLD, "make_segment_example.py"))
+    gen = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(gen)
+    with open(os.path.join(GOLD, "segment_example.json")) as f:
+        stored = json.load(f, parse_float=decimal.Decimal)
+    assert stored == json.loads(gen.text(), parse_float=decimal.Decimal)
+
+
 @pytest.mark.parametrize("eps_key", ["eps", "zero"])
 def test_segment_example_exhaustive(eps_key):
     g = _gold("segment_example.json")
@@ -489,12 +504,45 @@ def test_joint_constructed_rollback():
     np.testing.assert_array_equal(res.L, L0)
 
 
-def test_joint_literal_reading_runs():
+def test_joint_literal_reading_sums_the_component():
+    """The literal reading of Alg. 2 re-searches and sums E over the
+    component alone.  On the constructed rollback image (a 2 x 2 dot Z inside
+    the block whose sample X is replaced) the two readings decide apart: the
+    dot's own error falls from 4 times its distance to segment XY to exactly 0
+    (each dot pixel now equals an LR colour), so the literal trial is kept,
+    while the affected set also counts the 60 other pixels of the block,
+    which end 0.588 away from segment YZ, and rolls back.  The kept literal
+    trial leaves those 60 pixels' Theta and E as they were (stale), unlike a
+    fresh search on the final I_down."""
     s = 8
-    I = _dot_image()
+    H = W = 24
+    X, Y, Z = (0.2, 0.2, 0.2), (0.6, 0.6, 0.6), (0.9, 0.1, 0.1)
+    I = np.empty((H, W, 3))
+    I[:] = Y
+    I[8:16, 8:16] = X
+    I[9:11, 9:11] = Z
     L0 = O.downsample_point(I, s)
-    res = O.joint_downsample(I, L0, s, reading="literal")
-    assert res.n_accepted[0] == 1
+    dot = np.array([9 * W + 9, 9 * W + 10, 10 * W + 9, 10 * W + 10])
+    init = O.search_exhaustive(I, L0, s)
+    lit = O.joint_downsample(I, L0, s, tau=O.TAU, max_iter=1, reading="literal")
+    aff = O.joint_downsample(I, L0, s, tau=O.TAU, max_iter=1)
+    assert len(lit.log) == 1 and len(aff.log) == 1
+    d = lit.log[0]
+    assert d.accepted and not aff.log[0].accepted
+    assert d.q_pstar == [(4, 9 * W + 9)]
+    assert d.e0 == pytest.approx(float(init.err[dot].sum()), abs=1e-15)
+    assert d.e0 > 4 * 0.6
+    assert d.e1 == 0.0
+    assert np.array_equal(lit.L[1, 1], np.array(Z))
+    # pixels of the block outside the component keep their initial (stale) E
+    blk = np.zeros((H, W), dtype=bool)
+    blk[8:16, 8:16] = True
+    blk.ravel()[dot] = False
+    rest = np.flatnonzero(blk)
+    np.testing.assert_array_equal(lit.err[rest], init.err[rest])
+    fresh = O.search_exhaustive(I, lit.L, s)
+    assert np.all(fresh.err[rest] > 0.5)
+    assert lit.err_sum_final < lit.err_sum_initial < float(fresh.err.sum())
 
 
 # ---------------------------------------------------------------------------
