@@ -71,6 +71,25 @@ def _theta(th: Theta) -> L.glu_theta:
     )
 
 
+def _per_pixel(buf, th_desc, H: int, W: int, device, name: str):
+    """A float32 (H, W) per-pixel output (E or grad_alpha) laid out with
+    Theta's row stride, as the C ABI writes it: allocated that way when
+    ``buf`` is None, else checked (a buffer with another row stride would be
+    written out of bounds or in the wrong places)."""
+    stride = th_desc.row_stride if th_desc is not None else W
+    if buf is None:
+        if H * W == 0:
+            return torch.empty((H, W), dtype=torch.float32, device=device)
+        return torch.empty((H, stride), dtype=torch.float32, device=device)[:, :W]
+    if not isinstance(buf, torch.Tensor) or buf.dtype != torch.float32 or tuple(buf.shape) != (H, W):
+        raise ValueError("%s must be a float32 (%d, %d) tensor" % (name, H, W))
+    if not buf.is_cuda:
+        raise ValueError("%s must be a GPU tensor" % name)
+    if H * W and ((W > 1 and buf.stride(1) != 1) or (H > 1 and buf.stride(0) != stride)):
+        raise ValueError("%s must have Theta's row stride (%d elements)" % (name, stride))
+    return buf
+
+
 def _params(s: int, k: int, eps: float, mode: str = "exhaustive", degenerate: bool = True) -> L.glu_params:
     if mode not in _MODES:
         raise ValueError("mode must be 'exhaustive', 'fast' or 'gnu'")
@@ -88,10 +107,12 @@ def empty_theta(H: int, W: int, device="cuda") -> Theta:
     )
 
 
-def downsample(I: torch.Tensor, s: int, mode: str = "point") -> torch.Tensor:
-    """Regular-grid (point) or box downsampling of I to ceil(H/s) x ceil(W/s)."""
+def downsample(I: torch.Tensor, s: int, mode: str = "point", out: torch.Tensor | None = None) -> torch.Tensor:
+    """Regular-grid (point) or box downsampling of I to ceil(H/s) x ceil(W/s)
+    (into ``out`` when given)."""
     h, w = lr_shape(I.shape[0], I.shape[1], s)
-    out = torch.empty((h, w, I.shape[2]), dtype=I.dtype, device=I.device)
+    if out is None:
+        out = torch.empty((h, w, I.shape[2]), dtype=I.dtype, device=I.device)
     m = {"point": L.GLU_DOWN_POINT, "box": L.GLU_DOWN_BOX}[mode]
     lib = L.load()
     L.check(lib.glu_downsample(C.byref(_img(I, "I")), C.byref(_img(out, "I_low")), int(s), m, _stream()))
@@ -105,8 +126,9 @@ def search(I, I_low, s, k=3, eps=EPS, mode="exhaustive", return_err=False, theta
     candidates (GLU_FLAG_NO_DEGENERATE)."""
     H, W = I.shape[:2]
     theta = theta if theta is not None else empty_theta(H, W, I.device)
-    if return_err and err is None:
-        err = torch.empty((H, W), dtype=torch.float32, device=I.device)
+    thd = _theta(theta)
+    if return_err or err is not None:
+        err = _per_pixel(err, thd, H, W, I.device, "err")
     p = _params(s, k, eps, mode, degenerate)
     lib = L.load()
     L.check(
@@ -114,7 +136,7 @@ def search(I, I_low, s, k=3, eps=EPS, mode="exhaustive", return_err=False, theta
             C.byref(_img(I, "I")),
             C.byref(_img(I_low, "I_low")),
             C.byref(p),
-            C.byref(_theta(theta)),
+            C.byref(thd),
             C.c_void_p(err.data_ptr() if err is not None and err.numel() else None),
             _stream(),
         )
@@ -186,11 +208,12 @@ def search_apply(
         theta = empty_theta(H, W, I.device)
     if out is None:
         out = torch.empty((H, W, T_low.shape[2]), dtype=T_low.dtype, device=I.device)
-    if return_err and err is None:
-        err = torch.empty((H, W), dtype=torch.float32, device=I.device)
+    thd = _theta(theta) if theta is not None else None
+    if return_err or err is not None:
+        err = _per_pixel(err, thd, H, W, I.device, "err")
     p = _params(s, k, eps, mode, degenerate)
     lib = L.load()
-    th = C.byref(_theta(theta)) if theta is not None else None
+    th = C.byref(thd) if thd is not None else None
     L.check(
         lib.glu_search_apply(
             C.byref(_img(I, "I")),
@@ -239,13 +262,14 @@ def apply_backward(theta: Theta, T_low, grad_T_hat, s, k=3, need_T_low=True, nee
                                        out_alpha)
     H, W = theta.shape
     Cn = T_low.shape[2]
+    thd = _theta(theta)
     gT = None
     if need_T_low:
         gT = out_T_low if out_T_low is not None else torch.empty(
             T_low.shape, dtype=torch.float32, device=T_low.device)
     ga = None
     if need_alpha:
-        ga = out_alpha if out_alpha is not None else torch.empty((H, W), dtype=torch.float32, device=T_low.device)
+        ga = _per_pixel(out_alpha, thd, H, W, T_low.device, "grad_alpha")
     p = _params(s, k, EPS)
     lib = L.load()
     ws_bytes = 0
@@ -255,7 +279,7 @@ def apply_backward(theta: Theta, T_low, grad_T_hat, s, k=3, need_T_low=True, nee
             workspace = torch.empty(max(1, ws_bytes // 4), dtype=torch.float32, device=T_low.device)
     L.check(
         lib.glu_apply_backward(
-            C.byref(_theta(theta)),
+            C.byref(thd),
             C.byref(_img(T_low, "T_low")),
             C.byref(p),
             C.byref(_img(grad_T_hat, "grad_T_hat")),
@@ -439,7 +463,9 @@ def _batch_item(it) -> L.glu_batch_item:
 
 
 class BatchPlan:
-    """Fused search + apply over many images in one persistent launch.
+    """Fused search + apply over many images: one launch per kernel variant
+    present (window class, pixels per strip, storage type, LDS table), one
+    workgroup per tile; a batch of one variant is a single launch.
 
     items: list of dicts with I, I_low, T_low, T_hat (tensors), s, k and an
     optional Theta.  The tensors must stay alive while the plan is used.

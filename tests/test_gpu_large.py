@@ -71,33 +71,43 @@ def test_search_apply_backward_beyond_2_31_elements():
         check_search(Ic, Lh[cy0:cy1, cx0:cx1], S, K, 1e-3, "exhaustive", code, alpha, err=e, pixels=p,
                      T_low=Th[cy0:cy1, cx0:cx1], T_hat=That)
     del out, err
-    # backward: dalpha at the sampled pixels, grad_T_low at sampled cells
+    # backward: dalpha at the sampled pixels, grad_T_low at sampled cells,
+    # each against the oracle's gradient of Eq. 1 on a crop
     G = torch.randn(I.shape, generator=g, device=dev)
     gT, ga = glu.apply_backward(th, T, G, S, K)
     torch.cuda.synchronize()
+
+    def crop_backward(y0, y1, x0, x1, ly0, ly1, lx0, lx1, Gc):
+        """Oracle gradients of Eq. 1 for the HR pixels [y0, y1) x [x0, x1)
+        with LR indices relative to the LR crop [ly0, ly1) x [lx0, lx1)."""
+        code = host(th.code[y0:y1, x0:x1]).astype(np.int64) & 0xFFFF
+        al = host(th.alpha[y0:y1, x0:x1]).astype(np.float64)
+        yy, xx = np.mgrid[y0:y1, x0:x1]
+        o_a, o_b = np.divmod(code, K * K)
+        lw = lx1 - lx0
+        a = (yy // S + o_a // K - r - ly0) * lw + (xx // S + o_a % K - r - lx0)
+        b = (yy // S + o_b // K - r - ly0) * lw + (xx // S + o_b % K - r - lx0)
+        return O.apply_backward(a, b, al, Th[ly0:ly1, lx0:lx1], Gc)
+
     for y, x in zip(ys[:100].tolist(), xs[:100].tolist()):
-        o_a, o_b = divmod(int(th.code[y, x]) & 0xFFFF, K * K)
-        qy, qx = y // S, x // S
-        ay, ax = qy + o_a // K - r, qx + o_a % K - r
-        by, bx = qy + o_b // K - r, qx + o_b % K - r
-        ref = float(np.dot(host(G[y, x]).astype(np.float64), Th[ay, ax].astype(np.float64) - Th[by, bx]))
+        ly0, ly1, _, _ = _crop_bounds(y // S, h, H, r)
+        lx0, lx1, _, _ = _crop_bounds(x // S, w, W, r)
+        d_alpha, _ = crop_backward(y, y + 1, x, x + 1, ly0, ly1, lx0, lx1, host(G[y : y + 1, x : x + 1]))
+        ref = float(d_alpha[0, 0])
         assert abs(float(ga[y, x]) - ref) <= 1e-5 * (1 + abs(ref))
     cells = [(0, 0), (h - 1, w - 1), (h // 2, w // 3), (h - 1, 0), (0, w - 1)]
     cells += [(int(rng.integers(0, h)), int(rng.integers(0, w))) for _ in range(25)]
     for qy, qx in cells:
-        # pixels that can reach (qy, qx): blocks within r of it
-        cy0, cy1, y0, y1 = _crop_bounds(qy, h, H, r)
-        cx0, cx1, x0, x1 = _crop_bounds(qx, w, W, r)
-        code = host(th.code[y0:y1, x0:x1]).astype(np.int64) & 0xFFFF
-        al = host(th.alpha[y0:y1, x0:x1]).astype(np.float64)
+        # pixels that can reach (qy, qx): the blocks within r of it, whose
+        # windows lie within 2 r of it
+        _, _, y0, y1 = _crop_bounds(qy, h, H, r)
+        _, _, x0, x1 = _crop_bounds(qx, w, W, r)
+        ly0, ly1, _, _ = _crop_bounds(qy, h, H, 2 * r)
+        lx0, lx1, _, _ = _crop_bounds(qx, w, W, 2 * r)
         Gc = host(G[y0:y1, x0:x1]).astype(np.float64)
-        yy, xx = np.mgrid[y0:y1, x0:x1]
-        o_a, o_b = np.divmod(code, K * K)
-        ay, ax = yy // S + o_a // K - r, xx // S + o_a % K - r
-        by, bx = yy // S + o_b // K - r, xx // S + o_b % K - r
-        hit_a = (ay == qy) & (ax == qx)
-        hit_b = (by == qy) & (bx == qx)
-        ref = (al[..., None] * Gc * hit_a[..., None]).sum((0, 1)) + ((1 - al)[..., None] * Gc * hit_b[..., None]).sum((0, 1))
-        mass = (al[..., None] * np.abs(Gc) * hit_a[..., None]).sum((0, 1)) + ((1 - al)[..., None] * np.abs(Gc) * hit_b[..., None]).sum((0, 1))
+        _, dT = crop_backward(y0, y1, x0, x1, ly0, ly1, lx0, lx1, Gc)
+        _, mass = crop_backward(y0, y1, x0, x1, ly0, ly1, lx0, lx1, np.abs(Gc))
+        ref = dT[qy - ly0, qx - lx0]
+        m = mass[qy - ly0, qx - lx0]
         got = host(gT[qy, qx]).astype(np.float64)
-        assert np.all(np.abs(got - ref) <= 1e-5 * mass + 1e-12), (qy, qx, got, ref)
+        assert np.all(np.abs(got - ref) <= 1e-5 * m + 1e-12), (qy, qx, got, ref)

@@ -213,6 +213,51 @@ def test_padded_rows_and_views():
 
 
 @pytest.mark.parametrize("mode", ["exhaustive", "fast"])
+def test_padded_theta_err_and_grad_alpha(mode):
+    """E and grad_alpha share Theta's row stride in the C ABI: with a padded
+    Theta the binding lays them out (or checks them) with that stride, the
+    values equal those of a dense Theta and the padding is never written."""
+    glu = _glu()
+    log_case(test="padded_theta", mode=mode)
+    H, W, s, pad = 64, 100, 4, 12
+    I, L, T = _inputs(H, W, s, seed=23, n_cells=10, n_dots=4)
+    dI, dL, dT = dev(I), dev(L), dev(T)
+
+    def padded_theta():
+        code = torch.full((H, W + pad), -7, dtype=torch.int16, device="cuda")
+        alpha = torch.full((H, W + pad), 7.0, dtype=torch.float32, device="cuda")
+        return glu.Theta(code[:, :W], alpha[:, :W]), code, alpha
+
+    th0, e0 = glu.search(dI, dL, s, 3, 1e-3, mode, return_err=True)
+    thp, code_p, alpha_p = padded_theta()
+    _, ep = glu.search(dI, dL, s, 3, 1e-3, mode, return_err=True, theta=thp)
+    assert ep.stride(0) == W + pad
+    assert torch.equal(thp.code, th0.code) and torch.equal(thp.alpha, th0.alpha) and torch.equal(ep, e0)
+    assert bool((code_p[:, W:] == -7).all()) and bool((alpha_p[:, W:] == 7.0).all())
+    # a caller's buffer must have Theta's row stride
+    with pytest.raises(ValueError):
+        glu.search(dI, dL, s, 3, 1e-3, mode, return_err=True, theta=thp, err=torch.empty((H, W), device="cuda"))
+    eb = torch.full((H, W + pad), 9.0, device="cuda")
+    glu.search(dI, dL, s, 3, 1e-3, mode, return_err=True, theta=thp, err=eb[:, :W])
+    assert torch.equal(eb[:, :W], e0) and bool((eb[:, W:] == 9.0).all())
+
+    out0, _, ef0 = glu.search_apply(dI, dL, dT, s, 3, 1e-3, mode, return_err=True)
+    thq, _, _ = padded_theta()
+    outq, _, efq = glu.search_apply(dI, dL, dT, s, 3, 1e-3, mode, return_err=True, theta=thq)
+    assert efq.stride(0) == W + pad and torch.equal(efq, ef0) and torch.equal(outq, out0)
+
+    G = torch.randn((H, W, 3), device="cuda", generator=torch.Generator("cuda").manual_seed(24))
+    gT0, ga0 = glu.apply_backward(th0, dT, G, s, 3)
+    gTp, gap = glu.apply_backward(thp, dT, G, s, 3)
+    assert gap.stride(0) == W + pad and torch.equal(gap, ga0) and torch.equal(gTp, gT0)
+    gb = torch.full((H, W + pad), 5.0, device="cuda")
+    glu.apply_backward(thp, dT, G, s, 3, out_alpha=gb[:, :W])
+    assert torch.equal(gb[:, :W], ga0) and bool((gb[:, W:] == 5.0).all())
+    with pytest.raises(ValueError):
+        glu.apply_backward(thp, dT, G, s, 3, out_alpha=torch.empty((H, W), device="cuda"))
+
+
+@pytest.mark.parametrize("mode", ["exhaustive", "fast"])
 def test_full_4k_x8_sampled(mode):
     """The 3840 x 2160 x8 workload, in the launch configuration the benchmark
     times (fused search + apply), checked on sampled pixels: 20000 random
