@@ -83,28 +83,30 @@ __global__ __launch_bounds__(256) void k_jd_mark(const float* __restrict__ E, in
 }
 
 // exclusive scan of the tile counts by one workgroup: each thread sums a
-// contiguous run of tiles, thread 0 scans the 256 run totals, and each
+// contiguous run of tiles, the 256 run totals are scanned with wave
+// shuffles (inclusive scan per wave, then the wave totals), and each
 // thread writes its run's offsets
 __global__ __launch_bounds__(256) void k_jd_scan(const int* __restrict__ cnt, int ntiles, int* __restrict__ off,
                                                  int* __restrict__ total) {
-  __shared__ int run_sum[256];
+  __shared__ int wave_sum[4];
   const int per = (ntiles + 255) / 256;
   const int t0 = min(ntiles, (int)threadIdx.x * per), t1 = min(ntiles, t0 + per);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   int v = 0;
   for (int i = t0; i < t1; ++i) v += cnt[i];
-  run_sum[threadIdx.x] = v;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int acc = 0;
-    for (int i = 0; i < 256; ++i) {
-      const int c = run_sum[i];
-      run_sum[i] = acc;
-      acc += c;
-    }
-    total[0] = acc;
+  int inc = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int u = __shfl_up(inc, d, 64);
+    inc += lane >= d ? u : 0;
   }
+  if (lane == 63) wave_sum[wave] = inc;
   __syncthreads();
-  int acc = run_sum[threadIdx.x];
+  int base = 0;
+#pragma unroll
+  for (int w = 0; w < 4; ++w) base += w < wave ? wave_sum[w] : 0;
+  if (threadIdx.x == 255) total[0] = base + inc;
+  int acc = base + inc - v;
   for (int i = t0; i < t1; ++i) {
     const int c = cnt[i];
     off[i] = acc;
@@ -164,10 +166,12 @@ __device__ __forceinline__ void uf_unite(int* parent, int a, int b) {
   }
 }
 
+// union and flatten read the list length from the device and stride over
+// the list, so the host can launch them before it knows the length
 __global__ __launch_bounds__(256) void k_jd_union(int* __restrict__ parent, const int* __restrict__ list,
                                                   const int* __restrict__ total, int H, int W) {
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= total[0]) return;
+  const int nl = total[0];
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < nl; i += gridDim.x * 256) {
   const int p = list[i];
   const int y = p / W, x = p - y * W;
   // the four neighbours that precede p in raster order
@@ -178,46 +182,68 @@ __global__ __launch_bounds__(256) void k_jd_union(int* __restrict__ parent, cons
     if (__atomic_load_n(&parent[up], __ATOMIC_RELAXED) >= 0) uf_unite(parent, p, up);
     if (x + 1 < W && __atomic_load_n(&parent[up + 1], __ATOMIC_RELAXED) >= 0) uf_unite(parent, p, up + 1);
   }
+  }
 }
 
 __global__ __launch_bounds__(256) void k_jd_flatten(int* __restrict__ parent, const int* __restrict__ list,
                                                     const int* __restrict__ total, int* __restrict__ root) {
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= total[0]) return;
-  root[i] = uf_find(parent, list[i]);
+  const int nl = total[0];
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < nl; i += gridDim.x * 256) root[i] = uf_find(parent, list[i]);
 }
 
-// float64 sum of E in a fixed order: per tile, then one workgroup over tiles
+// float64 sum of E in a fixed order: per tile, then one workgroup over
+// tiles; each reduces with wave shuffles (a fixed tree per wave) and adds
+// the four wave sums in order
+__device__ __forceinline__ double block_sum256(double v) {
+  __shared__ double wsum[4];
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) v += __shfl_down(v, d, 64);
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = v;
+  __syncthreads();
+  const double r = ((wsum[0] + wsum[1]) + wsum[2]) + wsum[3];
+  __syncthreads();  // wsum may be written again by a later call
+  return r;
+}
+
+// exclusive scan of one int per thread over a workgroup of 256 (wave
+// shuffles, then the wave totals); *total gets the sum
+__device__ __forceinline__ int block_exclusive_scan256(int v, int* total) {
+  __shared__ int wtot[4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int inc = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int u = __shfl_up(inc, d, 64);
+    inc += lane >= d ? u : 0;
+  }
+  if (lane == 63) wtot[wave] = inc;
+  __syncthreads();
+  int base = 0;
+#pragma unroll
+  for (int w = 0; w < 4; ++w) base += w < wave ? wtot[w] : 0;
+  *total = wtot[0] + wtot[1] + wtot[2] + wtot[3];
+  __syncthreads();
+  return base + inc - v;
+}
+
 __global__ __launch_bounds__(256) void k_jd_sum_tiles(const float* __restrict__ E, int64_t n,
                                                       double* __restrict__ partial) {
-  __shared__ double s[256];
   const int64_t base = (int64_t)blockIdx.x * kTilePx;
   double v = 0.0;
   for (int u = 0; u < 4; ++u) {
     const int64_t p = base + u * 256 + threadIdx.x;
     if (p < n) v += (double)E[p];
   }
-  s[threadIdx.x] = v;
-  __syncthreads();
-  for (int d = 128; d > 0; d >>= 1) {
-    if (threadIdx.x < d) s[threadIdx.x] += s[threadIdx.x + d];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) partial[blockIdx.x] = s[0];
+  v = block_sum256(v);
+  if (threadIdx.x == 0) partial[blockIdx.x] = v;
 }
 
 __global__ __launch_bounds__(256) void k_jd_sum_final(double* __restrict__ partial, int ntiles,
                                                       double* __restrict__ out) {
-  __shared__ double s[256];
   double v = 0.0;
   for (int i = threadIdx.x; i < ntiles; i += 256) v += partial[i];
-  s[threadIdx.x] = v;
-  __syncthreads();
-  for (int d = 128; d > 0; d >>= 1) {
-    if (threadIdx.x < d) s[threadIdx.x] += s[threadIdx.x + d];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) out[0] = s[0];
+  v = block_sum256(v);
+  if (threadIdx.x == 0) out[0] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -240,18 +266,6 @@ struct JdTrialArgs {
 // comp[8 * c + ...]: 0 px_off, 1 n_px, 2 q_off, 3 n_q, 4 slot (sequential
 // index), 5 bbox y0, 6 bbox x0, 7 bbox packed (y1 << 16 | x1) of the
 // affected cells (inclusive, clamped to the LR image).
-
-__device__ __forceinline__ double block_sum(double v, double* s) {
-  s[threadIdx.x] = v;
-  __syncthreads();
-  for (int d = 128; d > 0; d >>= 1) {
-    if (threadIdx.x < d) s[threadIdx.x] += s[threadIdx.x + d];
-    __syncthreads();
-  }
-  const double r = s[0];
-  __syncthreads();
-  return r;
-}
 
 // One pixel's search against the current LR guide.  For 3 x 3 windows the
 // nine cells are read once into registers; other windows read them from
@@ -286,10 +300,7 @@ constexpr int kTrialCells = 4096;
 
 template <int KW>
 __global__ __launch_bounds__(256) void k_jd_trial(const JdTrialArgs a) {
-  __shared__ double red[256];
   __shared__ int s_cells[kTrialCells];
-  __shared__ int s_cnt[256];
-  __shared__ int s_naff;
   const int* cm = a.b.comp + 8 * (a.comp_begin + blockIdx.x);
   const int q_off = cm[2], n_q = cm[3], slot = cm[4];
   const int by0 = cm[5], bx0 = cm[6], by1 = cm[7] >> 16, bx1 = cm[7] & 0xffff;
@@ -319,6 +330,7 @@ __global__ __launch_bounds__(256) void k_jd_trial(const JdTrialArgs a) {
   // the list holds walks the whole box instead.
   const int ss = s * s;
   const int nbox = bw * bh;
+  int naff;  // affected cells (the same in every thread)
   {
     const int per = (nbox + 255) / 256;
     const int c0 = min(nbox, (int)threadIdx.x * per), c1 = min(nbox, c0 + per);
@@ -327,20 +339,8 @@ __global__ __launch_bounds__(256) void k_jd_trial(const JdTrialArgs a) {
       const int cy = by0 + c / bw, cx = bx0 + c % bw;
       cnt += __atomic_load_n(&a.b.flag[cy * a.w + cx], __ATOMIC_RELAXED) == mark;
     }
-    s_cnt[threadIdx.x] = cnt;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      int acc = 0;
-      for (int i = 0; i < 256; ++i) {
-        const int v = s_cnt[i];
-        s_cnt[i] = acc;
-        acc += v;
-      }
-      s_naff = acc;
-    }
-    __syncthreads();
-    if (s_naff <= kTrialCells) {
-      int o = s_cnt[threadIdx.x];
+    int o = block_exclusive_scan256(cnt, &naff);
+    if (naff <= kTrialCells) {
       for (int c = c0; c < c1; ++c) {
         const int cy = by0 + c / bw, cx = bx0 + c % bw;
         if (__atomic_load_n(&a.b.flag[cy * a.w + cx], __ATOMIC_RELAXED) == mark) s_cells[o++] = c;
@@ -348,8 +348,8 @@ __global__ __launch_bounds__(256) void k_jd_trial(const JdTrialArgs a) {
     }
     __syncthreads();
   }
-  const bool listed = s_naff <= kTrialCells;
-  const int64_t nslots = (int64_t)(listed ? s_naff : nbox) * ss;
+  const bool listed = naff <= kTrialCells;
+  const int64_t nslots = (int64_t)(listed ? naff : nbox) * ss;
   // pixel (y, x) of slot t; false for a slot outside the affected set
   auto slot_pixel = [&](int64_t t, int& y, int& x) -> bool {
     const int k = (int)(t / ss), within = (int)(t - (int64_t)k * ss);
@@ -367,7 +367,7 @@ __global__ __launch_bounds__(256) void k_jd_trial(const JdTrialArgs a) {
     if (!slot_pixel(t, y, x)) continue;
     e0 += (double)a.b.E[(int64_t)y * a.W + x];
   }
-  e0 = block_sum(e0, red);
+  e0 = block_sum256(e0);
 
   // p* per cell of Q (first largest E in raster order), save and replace
   for (int i = threadIdx.x; i < n_q; i += 256) {
@@ -411,7 +411,7 @@ __global__ __launch_bounds__(256) void k_jd_trial(const JdTrialArgs a) {
     a.b.st_err[p] = e;
     e1 += (double)e;
   }
-  e1 = block_sum(e1, red);
+  e1 = block_sum256(e1);
   const bool accept = !(e1 > e0);
 
   // commit or roll back; clear the flags
@@ -495,7 +495,7 @@ static JdLayout jd_layout(int64_t H, int64_t W, int s) {
   return L;
 }
 
-enum { PIN_SUM, PIN_TOTAL, PIN_LIST, PIN_ROOT, PIN_UP, PIN_DEC, PIN_PSTAR, PIN_N };
+enum { PIN_SUM, PIN_SUM0, PIN_TOTAL, PIN_LIST, PIN_ROOT, PIN_UP, PIN_DEC, PIN_PSTAR, PIN_N };
 static thread_local PinnedBuf tl_pin[PIN_N];
 
 static glu_status jd_sum(const float* E, int64_t n, double* partial, double* sums, hipStream_t st, double* out) {
@@ -592,40 +592,116 @@ glu_status glu_joint_downsample(const glu_image* I, glu_image* I_low, const glu_
   };
 
   if ((st = full_search())) return st;
-  double esum = 0.0;
-  if ((st = jd_sum(b.E, n, b.partial, sums, sm, &esum))) return st;
-  if (stats) stats->err_sum_initial = esum;
+  // the initial error sum: copied with the first round's data (one
+  // synchronisation per round; rounds_run = 0 reads it at the end)
+  hipLaunchKernelGGL(k_jd_sum_tiles, dim3((unsigned)ntiles), dim3(256), 0, sm, b.E, n, b.partial);
+  hipLaunchKernelGGL(k_jd_sum_final, dim3(1), dim3(256), 0, sm, b.partial, (int)ntiles, sums + 1);
+  e = tl_pin[PIN_SUM0].reserve(sizeof(double));
+  if (e == hipSuccess) e = hipMemcpyAsync(tl_pin[PIN_SUM0].p, sums + 1, sizeof(double), hipMemcpyDeviceToHost, sm);
+  if (e != hipSuccess) return hip_fail(e, "joint: initial error sum");
+  bool have_initial = false;
+  auto take_initial = [&]() {
+    if (!have_initial && stats) stats->err_sum_initial = *tl_pin[PIN_SUM0].as<double>();
+    have_initial = true;
+  };
+
+  // A round's decisions (accept flags, e0, e1, p*) are copied back after its
+  // trials without waiting; the host reads them at the next round's
+  // synchronisation (or after the loop), together with what it kept of the
+  // round's component table.
+  int64_t log_q_used = 0;
+  struct Pending {
+    int round = 0, total = 0, M = 0, levels = 0;
+    std::vector<int> first_pixel, cq_n, cq_off, qs;
+  } pend;
+  auto take_pending = [&]() {
+    if (pend.round == 0) return;
+    const int M = pend.M;
+    const double* dec = tl_pin[PIN_DEC].as<double>();
+    const int* pstar = tl_pin[PIN_PSTAR].as<int>();
+    int accepted = 0;
+    for (int c = 0; c < M; ++c) accepted += dec[3 * c] != 0.0;
+    if (stats) {
+      stats->rounds_run = pend.round;
+      stats->n_large[pend.round - 1] = pend.total;
+      stats->n_components[pend.round - 1] = M;
+      stats->n_accepted[pend.round - 1] = accepted;
+      stats->n_waves[pend.round - 1] = pend.levels;
+    }
+    if (log) {
+      for (int c = 0; c < M; ++c) {
+        if (log->count >= log->capacity) {
+          log->truncated = 1;
+          break;
+        }
+        const int i = log->count;
+        log->round[i] = pend.round;
+        log->first_pixel[i] = pend.first_pixel[c];
+        log->accepted[i] = dec[3 * c] != 0.0;
+        log->e0[i] = dec[3 * c + 1];
+        log->e1[i] = dec[3 * c + 2];
+        log->n_q[i] = pend.cq_n[c];
+        // q, p* pairs appended after the previous entries'
+        if (log->q_and_pstar && log_q_used + pend.cq_n[c] <= log->q_capacity) {
+          for (int j = 0; j < pend.cq_n[c]; ++j) {
+            log->q_and_pstar[2 * (log_q_used + j)] = pend.qs[pend.cq_off[c] + j];
+            log->q_and_pstar[2 * (log_q_used + j) + 1] = pstar[pend.cq_off[c] + j];
+          }
+        } else {
+          log->truncated = 1;
+        }
+        log->count = i + 1;
+        log_q_used += pend.cq_n[c];
+      }
+    }
+    pend.round = 0;
+  };
 
   std::vector<int> list, root, comp, qtab, pix, grid;
-  std::vector<double> dec;
-  std::vector<int> pstar;
-  int64_t log_q_used = 0;
+  // list entries copied with the count before the count is known: enough
+  // for the previous round's set twice over (a larger set takes a second copy)
+  int list_guess = 4096;
+  // union and flatten stride over the list with a small fixed grid
+  const unsigned ugrid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(64, (n + 255) / 256));
   for (int round = 1; round <= max_iter; ++round) {
     if (round > 1 && (st = full_search())) return st;
     hipLaunchKernelGGL(k_jd_mark, dim3((unsigned)ntiles), dim3(256), 0, sm, b.E, n, tau, b.parent, b.tile_count);
     hipLaunchKernelGGL(k_jd_scan, dim3(1), dim3(256), 0, sm, b.tile_count, (int)ntiles, b.tile_off, b.total);
     hipLaunchKernelGGL(k_jd_scatter, dim3((unsigned)ntiles), dim3(256), 0, sm, b.parent, n, b.tile_off, b.list);
-    int total = 0;
+    hipLaunchKernelGGL(k_jd_union, dim3(ugrid), dim3(256), 0, sm, b.parent, b.list, b.total, H, W);
+    hipLaunchKernelGGL(k_jd_flatten, dim3(ugrid), dim3(256), 0, sm, b.parent, b.list, b.total, b.list_root);
+    const int guess = (int)std::min<int64_t>(n, list_guess);
     e = tl_pin[PIN_TOTAL].reserve(sizeof(int));
+    if (e == hipSuccess) e = tl_pin[PIN_LIST].reserve(sizeof(int) * guess);
+    if (e == hipSuccess) e = tl_pin[PIN_ROOT].reserve(sizeof(int) * guess);
     if (e == hipSuccess) e = hipMemcpyAsync(tl_pin[PIN_TOTAL].p, b.total, sizeof(int), hipMemcpyDeviceToHost, sm);
+    if (e == hipSuccess) e = hipMemcpyAsync(tl_pin[PIN_LIST].p, b.list, sizeof(int) * guess, hipMemcpyDeviceToHost, sm);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(tl_pin[PIN_ROOT].p, b.list_root, sizeof(int) * guess, hipMemcpyDeviceToHost, sm);
     if (e == hipSuccess) e = hipStreamSynchronize(sm);
-    if (e != hipSuccess) return hip_fail(e, "joint: large-error count");
-    total = *tl_pin[PIN_TOTAL].as<int>();
+    if (e != hipSuccess) return hip_fail(e, "joint: large-error set");
+    take_initial();
+    take_pending();
+    const int total = *tl_pin[PIN_TOTAL].as<int>();
     if (total == 0) break;
-    const unsigned lg = (unsigned)((total + 255) / 256);
-    hipLaunchKernelGGL(k_jd_union, dim3(lg), dim3(256), 0, sm, b.parent, b.list, b.total, H, W);
-    hipLaunchKernelGGL(k_jd_flatten, dim3(lg), dim3(256), 0, sm, b.parent, b.list, b.total, b.list_root);
     list.resize(total);
     root.resize(total);
-    e = tl_pin[PIN_LIST].reserve(sizeof(int) * total);
-    if (e == hipSuccess) e = tl_pin[PIN_ROOT].reserve(sizeof(int) * total);
-    if (e == hipSuccess) e = hipMemcpyAsync(tl_pin[PIN_LIST].p, b.list, sizeof(int) * total, hipMemcpyDeviceToHost, sm);
-    if (e == hipSuccess)
-      e = hipMemcpyAsync(tl_pin[PIN_ROOT].p, b.list_root, sizeof(int) * total, hipMemcpyDeviceToHost, sm);
-    if (e == hipSuccess) e = hipStreamSynchronize(sm);
-    if (e != hipSuccess) return hip_fail(e, "joint: component labels");
-    std::memcpy(list.data(), tl_pin[PIN_LIST].p, sizeof(int) * total);
-    std::memcpy(root.data(), tl_pin[PIN_ROOT].p, sizeof(int) * total);
+    std::memcpy(list.data(), tl_pin[PIN_LIST].p, sizeof(int) * std::min(total, guess));
+    std::memcpy(root.data(), tl_pin[PIN_ROOT].p, sizeof(int) * std::min(total, guess));
+    if (total > guess) {
+      const int rest = total - guess;
+      e = tl_pin[PIN_LIST].reserve(sizeof(int) * rest);
+      if (e == hipSuccess) e = tl_pin[PIN_ROOT].reserve(sizeof(int) * rest);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(tl_pin[PIN_LIST].p, b.list + guess, sizeof(int) * rest, hipMemcpyDeviceToHost, sm);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(tl_pin[PIN_ROOT].p, b.list_root + guess, sizeof(int) * rest, hipMemcpyDeviceToHost, sm);
+      if (e == hipSuccess) e = hipStreamSynchronize(sm);
+      if (e != hipSuccess) return hip_fail(e, "joint: large-error set");
+      std::memcpy(list.data() + guess, tl_pin[PIN_LIST].p, sizeof(int) * rest);
+      std::memcpy(root.data() + guess, tl_pin[PIN_ROOT].p, sizeof(int) * rest);
+    }
+    list_guess = std::max(4096, 2 * total);
 
     // components in the order of their first pixel (= root, the smallest index)
     std::vector<int> order(total);
@@ -751,55 +827,30 @@ glu_status glu_joint_downsample(const glu_image* I, glu_image* I_low, const glu_
       e = hipGetLastError();
       if (e != hipSuccess) return hip_fail(e, "joint: trial launch");
     }
-    dec.resize(3 * (size_t)M);
-    pstar.resize(qtab.size() / 3);
-    e = tl_pin[PIN_DEC].reserve(sizeof(double) * dec.size());
-    if (e == hipSuccess) e = tl_pin[PIN_PSTAR].reserve(sizeof(int) * pstar.size());
+    // decisions: copied back now, read at the next synchronisation
+    e = tl_pin[PIN_DEC].reserve(sizeof(double) * 3 * (size_t)M);
+    if (e == hipSuccess) e = tl_pin[PIN_PSTAR].reserve(sizeof(int) * (qtab.size() / 3));
     if (e == hipSuccess)
-      e = hipMemcpyAsync(tl_pin[PIN_DEC].p, b.dec, sizeof(double) * dec.size(), hipMemcpyDeviceToHost, sm);
+      e = hipMemcpyAsync(tl_pin[PIN_DEC].p, b.dec, sizeof(double) * 3 * (size_t)M, hipMemcpyDeviceToHost, sm);
     if (e == hipSuccess)
-      e = hipMemcpyAsync(tl_pin[PIN_PSTAR].p, b.pstar, sizeof(int) * pstar.size(), hipMemcpyDeviceToHost, sm);
-    if (e == hipSuccess) e = hipStreamSynchronize(sm);
+      e = hipMemcpyAsync(tl_pin[PIN_PSTAR].p, b.pstar, sizeof(int) * (qtab.size() / 3), hipMemcpyDeviceToHost, sm);
     if (e != hipSuccess) return hip_fail(e, "joint: decisions");
-    std::memcpy(dec.data(), tl_pin[PIN_DEC].p, sizeof(double) * dec.size());
-    std::memcpy(pstar.data(), tl_pin[PIN_PSTAR].p, sizeof(int) * pstar.size());
-    int accepted = 0;
-    for (int c = 0; c < M; ++c) accepted += dec[3 * c] != 0.0;
-    if (stats) {
-      stats->rounds_run = round;
-      stats->n_large[round - 1] = total;
-      stats->n_components[round - 1] = M;
-      stats->n_accepted[round - 1] = accepted;
-      stats->n_waves[round - 1] = max_level;
-    }
-    if (log) {
-      for (int c = 0; c < M; ++c) {
-        const int64_t used = log_q_used;
-        if (log->count >= log->capacity) {
-          log->truncated = 1;
-          break;
-        }
-        const int i = log->count;
-        log->round[i] = round;
-        log->first_pixel[i] = list[order[cstart[c]]];
-        log->accepted[i] = dec[3 * c] != 0.0;
-        log->e0[i] = dec[3 * c + 1];
-        log->e1[i] = dec[3 * c + 2];
-        log->n_q[i] = cq_n[c];
-        // q, p* pairs appended after the previous entries'
-        if (log->q_and_pstar && used + cq_n[c] <= log->q_capacity) {
-          for (int j = 0; j < cq_n[c]; ++j) {
-            log->q_and_pstar[2 * (used + j)] = qtab[3 * (cq_off[c] + j)];
-            log->q_and_pstar[2 * (used + j) + 1] = pstar[cq_off[c] + j];
-          }
-        } else {
-          log->truncated = 1;
-        }
-        log->count = i + 1;
-        log_q_used += cq_n[c];
-      }
-    }
+    pend.round = round;
+    pend.total = total;
+    pend.M = M;
+    pend.levels = max_level;
+    pend.first_pixel.resize(M);
+    pend.cq_n.assign(cq_n.begin(), cq_n.end());
+    pend.cq_off.assign(cq_off.begin(), cq_off.end());
+    pend.qs.resize(qtab.size() / 3);
+    for (int c = 0; c < M; ++c) pend.first_pixel[c] = list[order[cstart[c]]];
+    for (size_t i = 0; i < pend.qs.size(); ++i) pend.qs[i] = qtab[3 * i];
   }
+  // the last round's decisions (and the initial sum when no round ran)
+  e = hipStreamSynchronize(sm);
+  if (e != hipSuccess) return hip_fail(e, "joint: decisions");
+  take_initial();
+  take_pending();
   // the returned Theta / E: the search against the final I_low
   {
     glu_theta th = *theta;
