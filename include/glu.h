@@ -247,6 +247,24 @@ glu_status glu_apply_backward_batched(int32_t n, const glu_batch_strides* stride
                                       const glu_image* grad_T_hat, glu_image* grad_T_low,
                                       float* grad_alpha, void* workspace, size_t ws_bytes, void* stream);
 
+/* glu_apply_backward_static - glu_apply_backward without a workspace
+ * argument and without any allocation, for callers that cannot allocate
+ * device memory (code under hipGraph capture, tight serving loops, hosts
+ * that forbid it).  The workspace is a library-owned device array of
+ * GLU_STATIC_SCRATCH_BYTES on each GPU the library runs on (held until the
+ * process ends); its address is looked up once per device, on the first
+ * call with that device current.  Arguments, layouts, results (bitwise)
+ * and errors are those of glu_apply_backward on the current device, plus
+ * GLU_ERR_WORKSPACE when glu_apply_backward_workspace() of the call exceeds
+ * GLU_STATIC_SCRATCH_BYTES (e.g. 3840 x 2160 at s = 8, k = 3, C = 3 needs
+ * 14.0 MiB).  Every call on one GPU shares that GPU's array: calls that
+ * overlap on one GPU (two streams, two threads) race and must be ordered
+ * by the caller.  Nothing in the array needs clearing between calls. */
+#define GLU_STATIC_SCRATCH_BYTES ((size_t)16 << 20)
+glu_status glu_apply_backward_static(const glu_theta* theta, const glu_image* T_low, const glu_params* p,
+                                     const glu_image* grad_T_hat, glu_image* grad_T_low, float* grad_alpha,
+                                     void* stream);
+
 /* ---------------------------------------------------------------------------
  * glu_downsample - initial LR guide (not on the timed path).
  *   POINT: I_low[q] = I[min(qy s + s/2, H-1), min(qx s + s/2, W-1)] (a copy

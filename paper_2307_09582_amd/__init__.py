@@ -16,6 +16,7 @@ from .glu import (  # noqa: F401
     autotune_save,
     apply,
     apply_backward,
+    apply_backward_static,
     apply_backward_workspace,
     apply_backward_batched_workspace,
     downsample,

@@ -28,6 +28,7 @@ GLU_F32, GLU_F16 = 0, 1
 GLU_SEARCH_EXHAUSTIVE, GLU_SEARCH_FAST, GLU_SEARCH_GNU = 0, 1, 2
 GLU_FLAG_NO_DEGENERATE = 1
 GLU_DOWN_POINT, GLU_DOWN_BOX = 0, 1
+GLU_STATIC_SCRATCH_BYTES = 16 << 20
 
 
 class GluError(RuntimeError):
@@ -150,6 +151,9 @@ _SIGS = {
             C.c_size_t,
             C.c_void_p,
         ],
+    ),
+    "glu_apply_backward_static": (
+        C.c_int, [P(glu_theta), P(glu_image), P(glu_params), P(glu_image), P(glu_image), C.c_void_p, C.c_void_p],
     ),
     "glu_downsample": (C.c_int, [P(glu_image), P(glu_image), C.c_int32, C.c_int32, C.c_void_p]),
     "glu_theta_expand": (C.c_int, [P(glu_theta), P(glu_params), C.c_void_p, C.c_void_p, C.c_void_p]),

@@ -31,6 +31,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "glu_device.h"
 #include "glu_host.h"
@@ -647,6 +648,34 @@ static void bwd_geometry(int s, int k, int w, int& nb, int& rows_chunk) {
   while (nb > 1 && 16 * bwd_lds_words(k, nb, s, rows_chunk) > 32 * 1024) nb = (nb + 1) / 2;
 }
 
+// The workspace of glu_apply_backward_static: one array per device (each GPU
+// holds its own copy at its own address).  Host code uses only the address
+// hipGetSymbolAddress returns for the current device, never the array's
+// name, which on the host is a stand-in, not a device address.
+static __device__ __align__(256) char scratch[GLU_STATIC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices];
+
+// Device address of the current device's array, looked up on the first
+// call with that device current.
+static glu_status static_scratch(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "static scratch: current device");
+  if (dev < 0 || dev >= kMaxDevices) return fail(GLU_ERR_UNSUPPORTED, "device %d beyond %d", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "static scratch address");
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return GLU_OK;
+}
+
 }  // namespace glu
 
 using namespace glu;
@@ -783,6 +812,25 @@ glu_status glu_apply_backward_batched(int32_t n, const glu_batch_strides* stride
   clear_error();
   return backward_batched(n, strides, theta, T_low, p, grad_T_hat, grad_T_low, grad_alpha, workspace, ws_bytes,
                           stream);
+}
+
+glu_status glu_apply_backward_static(const glu_theta* theta, const glu_image* T_low, const glu_params* p,
+                                     const glu_image* grad_T_hat, glu_image* grad_T_low, float* grad_alpha,
+                                     void* stream) {
+  clear_error();
+  void* ws = nullptr;
+  if (grad_T_low) {
+    if (!p) return fail(GLU_ERR_NULL, "params is NULL");
+    if (!grad_T_hat || !T_low) return fail(GLU_ERR_NULL, "image descriptor is NULL");
+    const size_t need = glu_apply_backward_workspace(grad_T_hat->height, grad_T_hat->width, T_low->channels, p);
+    if (need > GLU_STATIC_SCRATCH_BYTES)
+      return fail(GLU_ERR_WORKSPACE, "workspace of %zu bytes needed, the static array holds %zu", need,
+                  (size_t)GLU_STATIC_SCRATCH_BYTES);
+    glu_status st = static_scratch(&ws);
+    if (st) return st;
+  }
+  return backward_batched(1, nullptr, theta, T_low, p, grad_T_hat, grad_T_low, grad_alpha, ws,
+                          GLU_STATIC_SCRATCH_BYTES, stream);
 }
 
 }  // extern "C"

@@ -293,6 +293,35 @@ def apply_backward(theta: Theta, T_low, grad_T_hat, s, k=3, need_T_low=True, nee
     return gT, ga
 
 
+def apply_backward_static(theta: Theta, T_low, grad_T_hat, s, k=3, need_T_low=True, need_alpha=True, out_T_low=None,
+                          out_alpha=None):
+    """apply_backward through glu_apply_backward_static: no workspace and no
+    allocation in the library (the outputs are allocated here when not given);
+    calls on one GPU share the library's array and must not overlap."""
+    H, W = theta.shape
+    thd = _theta(theta)
+    gT = None
+    if need_T_low:
+        gT = out_T_low if out_T_low is not None else torch.empty(
+            T_low.shape, dtype=torch.float32, device=T_low.device)
+    ga = None
+    if need_alpha:
+        ga = _per_pixel(out_alpha, thd, H, W, T_low.device, "grad_alpha")
+    p = _params(s, k, EPS)
+    L.check(
+        L.load().glu_apply_backward_static(
+            C.byref(thd),
+            C.byref(_img(T_low, "T_low")),
+            C.byref(p),
+            C.byref(_img(grad_T_hat, "grad_T_hat")),
+            C.byref(_img(gT, "grad_T_low")) if gT is not None else None,
+            C.c_void_p(ga.data_ptr() if ga is not None and ga.numel() else None),
+            _stream(),
+        )
+    )
+    return gT, ga
+
+
 def apply_backward_batched_workspace(B: int, H: int, W: int, channels: int, s: int, k: int = 3) -> int:
     lib = L.load()
     p = _params(s, k, EPS)

@@ -196,3 +196,22 @@ def test_joint_downsampling_rejects_flags():
     st = lib.glu_joint_downsample(C.byref(I), C.byref(Il), C.byref(p), 30.0 / 255, 3, C.byref(th), 0x7000,
                                   0x100000, wsj, None, None, None)
     assert st == 8 and b"flags" in lib.glu_last_error()
+
+
+def test_static_backward_rejects_sizes_beyond_its_array():
+    """glu_apply_backward_static checks the workspace a call needs against its
+    fixed array before any device call: too large is GLU_ERR_WORKSPACE."""
+    lib = L.load()
+    p = _params(s=1, k=3)
+    H, W = 1024, 1024  # 1024^2 cells x 9 offsets x 3 channels x 4 bytes = 108 MiB
+    need = lib.glu_apply_backward_workspace(H, W, 3, C.byref(p))
+    assert need > L.GLU_STATIC_SCRATCH_BYTES
+    th = L.glu_theta(0x1000, 0x2000, H, W, W)
+    Tl = _img(ptr=0x3000, H=H, W=W, Cn=3)
+    G = _img(ptr=0x4000, H=H, W=W, Cn=3)
+    gT = _img(ptr=0x5000, H=H, W=W, Cn=3)
+    st = lib.glu_apply_backward_static(C.byref(th), C.byref(Tl), C.byref(p), C.byref(G), C.byref(gT), None, None)
+    assert st == 9, lib.glu_last_error()
+    assert b"static array" in lib.glu_last_error()
+    st = lib.glu_apply_backward_static(C.byref(th), C.byref(Tl), None, C.byref(G), C.byref(gT), None, None)
+    assert st == 1
