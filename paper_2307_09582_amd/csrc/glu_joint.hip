@@ -614,19 +614,20 @@ glu_status glu_joint_downsample(const glu_image* I, glu_image* I_low, const glu_
     int round = 0, total = 0, M = 0, levels = 0;
     std::vector<int> first_pixel, cq_n, cq_off, qs;
   } pend;
-  auto take_pending = [&]() {
-    if (pend.round == 0) return;
+  // stats and log entries of the pending round's decisions, reported as
+  // round `as_round`; returns the number of kept trials
+  auto emit_round = [&](int as_round) -> int {
     const int M = pend.M;
     const double* dec = tl_pin[PIN_DEC].as<double>();
     const int* pstar = tl_pin[PIN_PSTAR].as<int>();
     int accepted = 0;
     for (int c = 0; c < M; ++c) accepted += dec[3 * c] != 0.0;
     if (stats) {
-      stats->rounds_run = pend.round;
-      stats->n_large[pend.round - 1] = pend.total;
-      stats->n_components[pend.round - 1] = M;
-      stats->n_accepted[pend.round - 1] = accepted;
-      stats->n_waves[pend.round - 1] = pend.levels;
+      stats->rounds_run = as_round;
+      stats->n_large[as_round - 1] = pend.total;
+      stats->n_components[as_round - 1] = M;
+      stats->n_accepted[as_round - 1] = accepted;
+      stats->n_waves[as_round - 1] = pend.levels;
     }
     if (log) {
       for (int c = 0; c < M; ++c) {
@@ -635,7 +636,7 @@ glu_status glu_joint_downsample(const glu_image* I, glu_image* I_low, const glu_
           break;
         }
         const int i = log->count;
-        log->round[i] = pend.round;
+        log->round[i] = as_round;
         log->first_pixel[i] = pend.first_pixel[c];
         log->accepted[i] = dec[3 * c] != 0.0;
         log->e0[i] = dec[3 * c + 1];
@@ -654,7 +655,20 @@ glu_status glu_joint_downsample(const glu_image* I, glu_image* I_low, const glu_
         log_q_used += pend.cq_n[c];
       }
     }
+    return accepted;
+  };
+  // Reads the pending round.  A round that keeps no trial leaves I_low as
+  // it found it, so the next round's search, large-error set, components
+  // and trials are the same and decide the same: every later round repeats
+  // it decision for decision.  Those rounds are reported here without
+  // being run again; true means the loop is done.
+  auto take_pending = [&]() -> bool {
+    if (pend.round == 0) return false;
+    const int r0 = pend.round;
     pend.round = 0;
+    if (emit_round(r0) != 0) return false;
+    for (int r = r0 + 1; r <= max_iter; ++r) emit_round(r);
+    return true;
   };
 
   std::vector<int> list, root, comp, qtab, pix, grid;
@@ -681,7 +695,7 @@ glu_status glu_joint_downsample(const glu_image* I, glu_image* I_low, const glu_
     if (e == hipSuccess) e = hipStreamSynchronize(sm);
     if (e != hipSuccess) return hip_fail(e, "joint: large-error set");
     take_initial();
-    take_pending();
+    if (take_pending()) break;  // the previous round kept nothing: the rest repeat it
     const int total = *tl_pin[PIN_TOTAL].as<int>();
     if (total == 0) break;
     list.resize(total);
