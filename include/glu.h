@@ -173,8 +173,10 @@ glu_status glu_search(const glu_image* I, const glu_image* I_low, const glu_para
  *   theta  H x W, as written by glu_search (s, k in p must match).
  *   T_low  ceil(H/s) x ceil(W/s) x C, 1 <= C <= 4, GLU_F32 or GLU_F16.
  *   T_hat  output, H x W x C, same dtype as T_low.
- * Codes that point outside the LR image are not detected; they never come
- * out of glu_search.
+ * Codes that glu_search never writes have one defined meaning, shared with
+ * glu_apply_backward: a code above k^4 - 1 counts as k^4 - 1, and a window
+ * position outside the LR image reads the nearest in-image cell (its row
+ * and column clamped to the image).
  * ------------------------------------------------------------------------- */
 glu_status glu_apply(const glu_theta* theta, const glu_image* T_low, const glu_params* p,
                      glu_image* T_hat, void* stream);
@@ -230,7 +232,10 @@ glu_status glu_search_apply(const glu_image* I, const glu_image* I_low, const gl
  * grad_T_low is a gather over the inverted index map: each LR cell sums the
  * contributions of the HR pixels whose window can reach it in a fixed order
  * (per source block, then per window offset), without atomics, so the
- * result is bitwise reproducible.
+ * result is bitwise reproducible.  Codes glu_search never writes follow
+ * glu_apply's rule: the gradient of a window position outside the LR image
+ * goes to the clamped cell the apply reads, so the result is the gradient
+ * of what glu_apply computes.
  * ------------------------------------------------------------------------- */
 size_t glu_apply_backward_workspace(int32_t H, int32_t W, int32_t C, const glu_params* p);
 glu_status glu_apply_backward(const glu_theta* theta, const glu_image* T_low, const glu_params* p,
@@ -348,13 +353,14 @@ glu_status glu_joint_downsample_grad(const glu_image* I, glu_image* I_low, const
                                      int32_t* best_step /* HOST */, void* stream);
 
 /* ---------------------------------------------------------------------------
- * Batched persistent execution: search + apply of many images or frames of
- * any mix of sizes, ratios s, windows k and storage types.  The items are
- * grouped by kernel variant (window 3, 5 or other; 4 or 1 pixels per strip,
- * i.e. 4 | s or not; float32 or float16): each group runs in ONE persistent
- * launch of a kernel specialised for it, so a batch of one variant (the
- * frames of a video) is a single launch and a mixed batch one launch per
- * variant present, enqueued back to back on the stream.
+ * Batched execution: search + apply of many images or frames of any mix of
+ * sizes, ratios s, windows k and storage types.  The items are grouped by
+ * kernel variant (window 3, 5, 7 or other; pixels per strip; float32 or
+ * float16; LDS table or none): each group runs as ONE launch of a kernel
+ * specialised for it, with one workgroup per tile of the group's images, so
+ * a batch of one variant (the frames of a video) is a single launch and a
+ * mixed batch one launch per variant present, enqueued back to back on the
+ * stream.
  *
  * glu_batch_plan_create validates every item (same rules as
  * glu_search_apply, with the item's own s and k; eps and mode from p),

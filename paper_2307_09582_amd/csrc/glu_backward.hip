@@ -613,15 +613,39 @@ __global__ __launch_bounds__(256) void k_bwd_lr(const BwdArgs a0) {
   float acc[C];
 #pragma unroll
   for (int ch = 0; ch < C; ++ch) acc[ch] = 0.f;
+  // The cells c whose window offset o = (dy, dx) points at q.  A window
+  // position outside the LR image is read (by the apply) as the nearest
+  // in-image cell, so it sends its gradient there too: on a border row or
+  // column the sources are every c with clamp(c + d) = q, in ascending
+  // order; inside, only c = q - d.  Codes from the search never point
+  // outside the image, and then every extra source holds zero sums.
+  auto sources = [](int q, int dd, int n, int& lo, int& hi) {
+    if (n == 1) {
+      lo = 0;
+      hi = 0;
+    } else if (q == 0 && dd <= 0) {
+      lo = 0;
+      hi = min(n - 1, -dd);
+    } else if (q == n - 1 && dd >= 0) {
+      lo = max(0, n - 1 - dd);
+      hi = n - 1;
+    } else {
+      lo = hi = q - dd;  // empty when outside [0, n)
+      if (lo < 0 || lo >= n) hi = lo - 1;
+    }
+  };
   constexpr int kUnroll = KW > 0 ? KW * KW : 1;
 #pragma unroll kUnroll
   for (int o = 0; o < K2; ++o) {
-    // the cell c whose window offset o points at q: c = q - (o / k - r, o % k - r)
-    const int cy = qy - (o / k - r), cx = qx - (o % k - r);
-    const bool in = cy >= 0 && cy < a.h && cx >= 0 && cx < a.w;
-    const float* src = a.S + ((int64_t)o * hw + (in ? (int64_t)cy * a.w + cx : 0)) * C;
+    int y0, y1, x0, x1;
+    sources(qy, o / k - r, a.h, y0, y1);
+    sources(qx, o % k - r, a.w, x0, x1);
+    for (int cy = y0; cy <= y1; ++cy)
+      for (int cx = x0; cx <= x1; ++cx) {
+        const float* src = a.S + ((int64_t)o * hw + (int64_t)cy * a.w + cx) * C;
 #pragma unroll
-    for (int ch = 0; ch < C; ++ch) acc[ch] += in ? src[ch] : 0.0f;
+        for (int ch = 0; ch < C; ++ch) acc[ch] += src[ch];
+      }
   }
   float* out = a.dT + (int64_t)qy * a.dT_stride + (int64_t)qx * C;
 #pragma unroll

@@ -246,3 +246,49 @@ def test_batched_autograd_matches_loop():
         l1.backward()
         assert torch.allclose(a1.grad, ga[b], rtol=1e-6, atol=1e-12)
         assert torch.allclose(T1.grad, gT[b], rtol=1e-6, atol=1e-12)
+
+
+@pytest.mark.parametrize("H,W,s,k,C", [(64, 72, 8, 3, 3), (37, 41, 4, 5, 2), (20, 9, 4, 3, 1), (8, 8, 8, 3, 3)])
+def test_border_and_invalid_codes_follow_the_clamp_rule(H, W, s, k, C):
+    """Codes the search never writes: window positions outside the LR image
+    (at its borders) and codes above k^4 - 1.  The apply reads the nearest
+    in-image cell (clamped row and column; a code above k^4 - 1 counts as
+    k^4 - 1), and the backward sends each gradient to the same cell, so both
+    match the oracle's Eq. 1 and its gradient with those cells."""
+    glu = _glu()
+    log_case(test="backward_clamp_rule", H=H, W=W, s=s, k=k, C=C)
+    rng = np.random.default_rng(H * 31 + W)
+    h, w = -(-H // s), -(-W // s)
+    r, K2 = k // 2, k * k
+    oa = rng.integers(0, K2, (H, W))
+    ob = rng.integers(0, K2, (H, W))
+    code = (oa * K2 + ob).astype(np.uint16)
+    code[rng.random((H, W)) < 0.1] = 0xFFFF
+    alpha = rng.random((H, W)).astype(np.float32)
+    T = rng.random((h, w, C)).astype(np.float32)
+    G = rng.normal(0, 1, (H, W, C)).astype(np.float32)
+    # the rule, written out: clamp the code, then each cell into the image
+    cd = np.minimum(code.astype(np.int64), K2 * K2 - 1)
+    ys, xs = np.mgrid[0:H, 0:W]
+    qy, qx = ys // s, xs // s
+
+    def cell(o):
+        cy = np.clip(qy + o // k - r, 0, h - 1)
+        cx = np.clip(qx + o % k - r, 0, w - 1)
+        return (cy * w + cx).ravel()
+
+    a, b = cell(cd // K2), cell(cd % K2)
+    th = glu.Theta(dev(code.view(np.int16)), dev(alpha))
+    out = host(glu.apply(th, dev(T), s, k))
+    ref = O.apply(a, b, alpha.ravel(), T).reshape(H, W, C)
+    assert np.abs(out - ref).max() <= 1e-5
+    gT, ga = glu.apply_backward(th, dev(T), dev(G), s, k)
+    gT, ga = host(gT), host(ga)
+    da_ref, dT_ref = O.apply_backward(a, b, alpha.ravel(), T, G.reshape(-1, C))
+    assert np.all(np.abs(ga.ravel() - da_ref) <= 1e-5 * (1 + np.abs(da_ref)))
+    mass = np.zeros((h * w, C))
+    Gf = np.abs(G.reshape(-1, C).astype(np.float64))
+    np.add.at(mass, a, alpha.ravel()[:, None] * Gf)
+    np.add.at(mass, b, (1 - alpha.ravel())[:, None] * Gf)
+    err = np.abs(gT.reshape(-1, C) - dT_ref.reshape(-1, C))
+    assert np.all(err <= 1e-5 * mass + 1e-12), float((err / (mass + 1e-30)).max())
