@@ -83,8 +83,8 @@ glu_status check_theta(const glu_theta* th, int H, int W, bool need) {
 // ---------------------------------------------------------------------------
 // tiles
 // ---------------------------------------------------------------------------
-static const int kVariantCols[] = {64, 32, 128, 64, 32};
-static const int kVariantStripsPerThread[] = {1, 1, 1, 2, 2};
+static const int kVariantCols[] = {64, 32, 128, 64, 32, 64, 128, 128};
+static const int kVariantStripsPerThread[] = {1, 1, 1, 2, 2, 4, 2, 4};
 
 int n_tile_variants() { return (int)(sizeof(kVariantCols) / sizeof(kVariantCols[0])); }
 

@@ -1,4 +1,4 @@
-// Batched persistent execution and the tile autotuner.
+// Batched execution (one launch per kernel variant) and the tile autotuner.
 //
 // A plan holds a device table of image descriptors (any mix of sizes,
 // ratios s, windows k and storage types), grouped by kernel variant (window
@@ -55,7 +55,7 @@ static void set_tuned_variant(int mode, int k, int s, int dtype, int v) {
 }
 
 // ---------------------------------------------------------------------------
-// persistent kernel
+// batch kernel: one workgroup per tile of a variant group
 // ---------------------------------------------------------------------------
 struct BatchTable {
   const ImgDesc* items;

@@ -27,7 +27,7 @@ enum : uint32_t {
 };
 
 // One image of a search / apply launch.  The plain entry points launch one
-// of these; the batched persistent kernel walks a table of them.
+// of these; the batch kernel looks its tile's image up in a table of them.
 struct ImgDesc {
   const void* I;        // HR guide (3 channels)
   const void* L;        // LR guide (3 channels)
