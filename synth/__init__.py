@@ -48,6 +48,13 @@ __all__ = [
     "lr_op_f2",
     "COLOR_MATRIX",
     "uneven_batch_specs",
+    "noisy_crop_torch",
+    "lr_op_f1_torch",
+    "video_frames_torch",
+    "scene_4k",
+    "uneven_batch_torch",
+    "SCENE_4K",
+    "UNEVEN_CANVAS",
 ]
 
 # Row-stochastic colour matrix shared by both LR operators: rows are
@@ -214,3 +221,71 @@ def uneven_batch_specs(n: int = 64, seed: int = 4, wmin=720, wmax=6000, hmin=480
             )
         )
     return out
+
+
+# ---------------------------------------------------------------------------
+# Device-resident workloads (torch).  The noise is drawn on the device with
+# a seeded torch generator, so the benchmark and the tests that check the
+# same launches build bit-identical inputs; neither touches the upsampler.
+# ---------------------------------------------------------------------------
+
+# The 4K scene (seed 3, 1000 cells, 400 dots of 1-3 px, 177 extra columns);
+# frame t of the 4K video is its canvas crop at column 3 t, with device
+# noise seeded 7000 + t
+SCENE_4K = dict(H=2160, W=3840, n_cells=1000, n_dots=400, dot_px=(1, 3), seed=3, canvas_extra=177,
+                step_x=3, noise_seed0=7000)
+# uneven batch: crops of one 6000 x 4000 canvas (seed 4, cell and dot
+# density of the 4K scene), crop origins from default_rng(44)
+UNEVEN_CANVAS = dict(H=4000, W=6000, n_cells=2894, n_dots=1157, dot_px=(1, 3), seed=4, origin_seed=44)
+
+
+def noisy_crop_torch(canvas, y0, x0, h, w, seed, dtype, sigma=0.01):
+    """A crop of a noise-free canvas (a float32 device tensor) plus seeded
+    N(0, sigma^2) noise drawn on the canvas's device, clipped to [0, 1] and
+    cast to ``dtype``; contiguous."""
+    import torch
+
+    g = torch.Generator(device=canvas.device)
+    g.manual_seed(seed)
+    img = canvas[y0:y0 + h, x0:x0 + w]
+    noise = torch.randn(img.shape, generator=g, device=img.device, dtype=torch.float32)
+    return torch.clamp(img + sigma * noise, 0.0, 1.0).to(dtype).contiguous()
+
+
+def lr_op_f1_torch(c):
+    """LR operator f1 (colour matrix, then gamma 0.8) in float32 on the
+    tensor's device; returns float32 (..., 3)."""
+    import torch
+
+    M = torch.tensor(COLOR_MATRIX, dtype=torch.float32, device=c.device)
+    return torch.clamp(c.float() @ M.T, min=0.0) ** 0.8
+
+
+def scene_4k():
+    """The SCENE_4K scene (its canvas and frames)."""
+    v = SCENE_4K
+    return make_scene(v["H"], v["W"], v["n_cells"], v["n_dots"], v["dot_px"], v["seed"], v["canvas_extra"])
+
+
+def video_frames_torch(canvas, n, dtype):
+    """The ``n`` frames of the 4K video workload as device tensors, from the
+    float32 device copy of the SCENE_4K scene's canvas."""
+    v = SCENE_4K
+    return [noisy_crop_torch(canvas, 0, v["step_x"] * t, v["H"], v["W"], v["noise_seed0"] + t, dtype)
+            for t in range(n)]
+
+
+def uneven_batch_torch(canvas, specs, dtype):
+    """The uneven batch's images as device tensors: for each spec a crop of
+    the UNEVEN_CANVAS scene's canvas (float32 device copy) at an origin
+    drawn from default_rng(origin_seed), with device noise seeded by the
+    spec.  Returns the images and their (y0, x0) origins."""
+    Hc, Wc = canvas.shape[:2]
+    rng = np.random.default_rng(UNEVEN_CANVAS["origin_seed"])
+    imgs, origins = [], []
+    for sp in specs:
+        y0 = int(rng.integers(0, Hc - sp["H"] + 1))
+        x0 = int(rng.integers(0, Wc - sp["W"] + 1))
+        imgs.append(noisy_crop_torch(canvas, y0, x0, sp["H"], sp["W"], sp["seed"], dtype))
+        origins.append((y0, x0))
+    return imgs, origins

@@ -14,6 +14,10 @@ ulp + 1e-5 (float16).
 """
 from __future__ import annotations
 
+import concurrent.futures as cf
+import multiprocessing as mp
+import os
+
 import numpy as np
 
 import oracle as O
@@ -59,11 +63,13 @@ class ParityReport(dict):
 
 
 def check_search(I, L, s, k, eps, mode, code, alpha, err=None, pixels=None, T_low=None, T_hat=None,
-                 out_dtype=np.float32, degenerate=True):
+                 out_dtype=np.float32, degenerate=True, ref=None):
     """Runs the oracle on `pixels` (default all) and checks the GPU outputs.
 
     I, L, T_low: host arrays of the exact values the GPU consumed.
     code, alpha, err, T_hat: host copies of the GPU outputs (full images).
+    ref: the oracle's search result over `pixels` when it was computed
+    already (OraclePool.search); it is updated in place.
     Returns a report dict; raises AssertionError on a violation.
     """
     I = np.asarray(I)
@@ -79,7 +85,9 @@ def check_search(I, L, s, k, eps, mode, code, alpha, err=None, pixels=None, T_lo
     assert ok.all(), "GPU codes point outside the LR image at %d pixels" % int((~ok).sum())
     assert _in_window(a_g, pixels, W, s, k, h, w).all() and _in_window(b_g, pixels, W, s, k, h, w).all()
     al_g = np.asarray(alpha, dtype=np.float64).reshape(-1)[pixels]
-    if degenerate:
+    if ref is not None:
+        assert degenerate and ref.a.shape == pixels.shape
+    elif degenerate:
         ref = O.search(I, L, s, k, eps, mode, pixels=pixels)
     else:
         assert mode == "exhaustive", "the pairs-only candidate set is an exhaustive-search option"
@@ -166,3 +174,63 @@ def check_search(I, L, s, k, eps, mode, code, alpha, err=None, pixels=None, T_lo
                 float(dT.max()), int(pixels[np.argmax(dT.max(axis=1))]))
         rep["T_max_err"] = float(dT.max())
     return rep
+
+
+# ---------------------------------------------------------------------------
+# The oracle's search over many pixels, split across host processes.
+# ---------------------------------------------------------------------------
+
+def _pool_job(job):
+    """Worker side: the oracle's search of one chunk of pixels, all of them
+    in rows y0 .. y0 + len(rows) - 1 of an H x W image.  The search reads the
+    guide only at the searched pixels (and the LR guide in their windows), so
+    the worker places the rows into an otherwise empty full-size image (its
+    untouched pages are never allocated)."""
+    H, W, y0, rows, L, s, k, eps, mode, pix = job
+    I = np.zeros((H, W, rows.shape[2]), dtype=np.float64)
+    I[y0:y0 + rows.shape[0]] = rows
+    r = O.search(I, L, s, k, eps, mode, pixels=pix)
+    return r.a, r.b, r.alpha, r.err
+
+
+def pool_workers():
+    """Host cores this process may use, at most 16."""
+    return max(1, min(16, len(os.sched_getaffinity(0))))
+
+
+class OraclePool:
+    """A pool of spawned processes that run the oracle's search (they import
+    numpy and the oracle only, and never touch the GPU).  ``search`` returns
+    what one ``O.search`` call over the same pixels returns."""
+
+    def __init__(self, workers=None):
+        self.workers = workers or pool_workers()
+        self._ex = cf.ProcessPoolExecutor(self.workers, mp_context=mp.get_context("spawn"))
+
+    def close(self):
+        self._ex.shutdown(wait=True, cancel_futures=True)
+
+    def search(self, I, L, s, k, eps, mode, pixels=None, chunk=1 << 16):
+        I = np.asarray(I)
+        H, W = I.shape[:2]
+        if pixels is None:
+            pixels = np.arange(H * W, dtype=np.int64)
+        pixels = np.asarray(pixels, dtype=np.int64)
+        n_chunks = max(1, min(-(-pixels.size // chunk), 64 * self.workers))
+        jobs = []
+        for pix in np.array_split(pixels, n_chunks):
+            if pix.size == 0:
+                continue
+            ys = pix // W
+            y0, y1 = int(ys.min()), int(ys.max()) + 1
+            jobs.append((H, W, y0, np.asarray(I[y0:y1]), np.asarray(L), s, k, eps, mode, pix))
+        try:
+            parts = list(self._ex.map(_pool_job, jobs))
+        except cf.process.BrokenProcessPool:
+            self._ex.shutdown(wait=False, cancel_futures=True)
+            raise
+        if not parts:
+            e = np.zeros(0)
+            return O.SearchResult(a=e.astype(np.int64), b=e.astype(np.int64), alpha=e, err=e, pixels=pixels)
+        cat = lambda i: np.concatenate([p[i] for p in parts])
+        return O.SearchResult(a=cat(0), b=cat(1), alpha=cat(2), err=cat(3), pixels=pixels)
