@@ -16,7 +16,7 @@ modes (search, apply, fused, and the two-kernel step), the roofline of the
 dominant kernel, the backward pass, and one entry per further workload:
 plain 512 x 512 x4, joint downsampling 2048 x 2048 x8 (5 rounds of
 Algorithm 2, and 5 steps of the gradient-driven form), 60 x 4K
-float16 video frames in one graph-captured persistent launch, an uneven
+float16 video frames in one graph-captured launch, an uneven
 batch of 64 images with autotuned tiles, and the backward over 16 x 1024^2.
 """
 from __future__ import annotations
@@ -38,14 +38,20 @@ if ROOT not in sys.path:
 
 H, W, S, K, EPS = 2160, 3840, 8, 3, 1e-3
 HBM_PEAK_GBS = 8000.0
-FP32_VECTOR_PEAK_TFLOPS = 157.3
+FP32_VECTOR_PEAK_TFLOPS = 157.3  # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz x 2 (FMA) x 2 (dual issue)
+FP32_UNPACKED_PEAK_TFLOPS = 78.6  # the same with one VALU instruction per SIMD and cycle
+VALU_QUAD_CYCLES_PER_S = 1024 * 2.4e9 / 4  # 1024 SIMDs; a wave64 VALU instruction issues in 4 cycles
 
-# Algorithmic float32 operations per HR pixel of the search, k = 3 (9 cells,
-# 36 pairs).  Exhaustive: 27 (I - L_j for 9 cells) + 5 (|d_0|^2) + 36 x 17
-# (dot 5, weight 1, residual 6, squared norm 5).  Fast (Algorithm 1):
-# 9 x (3 + 5 + 1 sqrt) for the distances, then 9 x (1 + 1 + 1 division
-# + 1 + 6 + 6 + 5) for the partners.  The fused kernel adds Eq. 1 (3 x 2).
-FLOPS_PER_PX = {"exhaustive": 27 + 5 + 36 * 17, "fast": 9 * 9 + 9 * 21}
+# Algorithmic float32 operations per HR pixel of the search of a 3 x 3
+# window (9 cells, 36 pairs).  Exhaustive (Eq. 3-4): 13 per pair (the
+# projection dot product, the weight and its clamp, the residual and its
+# squared norm, the compare) plus 8 per cell (the pixel's offset from the
+# cell and its squared norm): 13 x 36 + 8 x 9 = 540.  Fast (Algorithm 1,
+# Eq. 5): 24 per cell (distance to the cell, then the partner's weight,
+# residual and norm): 24 x 9 = 216, with one square root and one
+# reciprocal per cell not counted.  The fused kernel adds Eq. 1, 2 per
+# target channel (6).
+FLOPS_PER_PX = {"exhaustive": 13 * 36 + 8 * 9, "fast": 24 * 9}
 APPLY_FLOPS_PER_PX = 6
 # Algorithmic HBM bytes per HR pixel (C = 3, float32): search reads I (12)
 # and writes Theta (6); apply reads Theta (6) and writes T_hat (12); fused
@@ -59,10 +65,14 @@ def _parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=300)
     ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--settle-ms", type=float, default=150.0,
+                    help="wall time of back-to-back steps run before the warmup steps (0: none)")
     ap.add_argument("--mode", choices=["exhaustive", "fast"], default="exhaustive")
     ap.add_argument("--sets", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=16.0,
+                    help="seconds of one-core oracle work on the 4K frame (both modes together)")
+    ap.add_argument("--cpu-child", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--only", choices=["all", "step"], default="all",
                     help="'step' times only the headline step (for profiling)")
     ap.add_argument("--no-configs", action="store_true", help="skip the further workloads")
@@ -118,9 +128,26 @@ def _events_ms(torch, stream, fn, steps, warmup):
     return e0.elapsed_time(e1) / steps
 
 
+def _settle(torch, fn, ms):
+    """Runs the step back to back for ``ms`` milliseconds of wall time, in
+    chunks of 64 with a synchronisation after each.  On a GPU that was idle
+    the first milliseconds of load see the clocks dip and recover (the
+    kernel trace shows a 4K fused step at 124 us, then 157 us for about
+    3 ms, then back to 115-120 us after about 25 ms); the timed steps
+    should not depend on where that dip falls."""
+    steps, t0 = 0, time.perf_counter()
+    while (time.perf_counter() - t0) * 1e3 < ms:
+        for _ in range(64):
+            fn(steps)
+            steps += 1
+        torch.cuda.synchronize()
+    return {"steps": steps, "ms": round((time.perf_counter() - t0) * 1e3, 1)}
+
+
 def _per_launch_us(torch, stream, fn, n, warmup):
-    """Median, p10 and p90 of n single launches, each bracketed by its own
-    pair of HIP events on `stream` (launches still queue back to back)."""
+    """Mean, median, p10 and p90 of n single launches, each bracketed by its
+    own pair of HIP events on `stream` (so one launch does not overlap the
+    next, as in a kernel trace)."""
     for i in range(warmup):
         fn(i)
     torch.cuda.synchronize()
@@ -131,7 +158,23 @@ def _per_launch_us(torch, stream, fn, n, warmup):
         b.record(stream)
     torch.cuda.synchronize()
     t = sorted(1e3 * a.elapsed_time(b) for a, b in ev)
-    return {"median": round(t[n // 2], 2), "p10": round(t[n // 10], 2), "p90": round(t[(9 * n) // 10], 2)}
+    return {"mean": round(sum(t) / n, 2), "median": round(t[n // 2], 2), "p10": round(t[n // 10], 2),
+            "p90": round(t[(9 * n) // 10], 2)}
+
+
+def _profile_entry(name: str, kernel_key: str):
+    """One kernel's entry of a committed profile summary, or None when the
+    kernel sources changed since the profile was taken."""
+    p = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(p):
+        return None
+    try:
+        t = json.load(open(p))
+    except Exception:
+        return None
+    if t.get("source_hash") != _kernel_source_hash():
+        return None
+    return t.get("kernels", {}).get(kernel_key)
 
 
 def _lr_f2_torch(torch, c):
@@ -150,26 +193,11 @@ def _lr_f2_torch(torch, c):
     return (blur @ M.T).contiguous()
 
 
-def _lr_f1_torch(torch, c):
-    """LR operator f1 (colour matrix, then gamma 0.8) on the GPU in float32."""
-    import synth
-
-    M = torch.tensor(synth.COLOR_MATRIX, dtype=torch.float32, device=c.device)
-    return torch.clamp(c.float() @ M.T, min=0.0) ** 0.8
-
-
-def _noisy_crop(torch, canvas_dev, y0, x0, h, w, seed, dtype):
-    """A crop of a noise-free Voronoi canvas plus seeded N(0, 0.01) noise
-    drawn on the GPU, clipped to [0, 1]."""
-    g = torch.Generator(device=canvas_dev.device)
-    g.manual_seed(seed)
-    img = canvas_dev[y0:y0 + h, x0:x0 + w]
-    noise = torch.randn(img.shape, generator=g, device=img.device, dtype=torch.float32)
-    return torch.clamp(img + 0.01 * noise, 0.0, 1.0).to(dtype).contiguous()
-
-
 def main():
     args = _parse()
+    if args.cpu_child:
+        _cpu_child(args.mode, args.cpu_seconds)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU: this GLU library runs on a single MI355X and does not shard "
@@ -186,7 +214,7 @@ def main():
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
     t0 = time.time()
-    scene = synth.make_scene(H, W, 1000, 400, (1, 3), seed=3, canvas_extra=177)
+    scene = synth.scene_4k()
     sets = []
     for t in range(args.sets):
         I = torch.from_numpy(scene.frame(t, sigma=0.01, dtype=np.float32)).to(dev)
@@ -226,9 +254,11 @@ def main():
             glu.apply(st["th"], st["T"], S, K, out=st["out"])
         return f
 
-    # headline: W warmup steps, then exactly K timed steps bracketed by
-    # synchronisation on both sides
+    # headline: a clock-settling phase, W warmup steps, then exactly K timed
+    # steps bracketed by synchronisation on both sides
     step = fused(args.mode)
+    settle = _settle(torch, step, args.settle_ms)
+    print("clock settle: %d steps in %.1f ms" % (settle["steps"], settle["ms"]), file=sys.stderr, flush=True)
     for i in range(args.warmup):
         step(i)
     torch.cuda.synchronize()
@@ -283,18 +313,39 @@ def main():
 
     roof = None
     if args.only == "all":
-        ks = kern[args.mode]
+        # the dominant (only) kernel of the step: algorithmic flops per launch
+        # over its average launch duration in the timed region (HIP events
+        # on its stream around the K back-to-back steps, one launch each)
+        key = "search_%s_fused" % args.mode
         flops = (FLOPS_PER_PX[args.mode] + APPLY_FLOPS_PER_PX) * n_px
-        achieved = flops / (ks["fused_us"] * 1e-6) / 1e12
+        dur_us = 1e3 * ms_step
+        achieved = flops / (dur_us * 1e-6) / 1e12
         roof = {
-            "kernel": "search_%s_fused" % args.mode,
+            "kernel": key,
             "bound": "alu",
             "achieved": round(achieved, 3),
             "peak": FP32_VECTOR_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
-            "traffic": _traffic("search_%s_fused" % args.mode),
+            "traffic": _traffic(key),
+            "flop_per_px": FLOPS_PER_PX[args.mode] + APPLY_FLOPS_PER_PX,
+            "duration_us": round(dur_us, 2),
+            "duration_source": "HIP events on the kernel's stream around the K timed steps (one launch each)",
+            "frac_of_unpacked_peak": round(achieved / FP32_UNPACKED_PEAK_TFLOPS, 4),
         }
+        tr = _profile_entry("kernels_4k_x8.json", key)
+        if tr:
+            roof["trace_timed_window_us"] = tr["timed_window_avg_us"]
+            roof["trace_source"] = "profiles/kernels_4k_x8.json: kernel-trace average over the timed steps"
+        vc = _profile_entry("valu_4k_x8.json", key)
+        if vc:
+            quad = dur_us * 1e-6 * VALU_QUAD_CYCLES_PER_S
+            roof["valu_issue"] = {
+                "instr_per_px": round(vc["valu_insts"] * 64 / n_px, 1),
+                "per_quad_cycle": round(vc["valu_insts"] / quad, 3),
+                "dual_issued_frac": round(2 * vc["valu2_quad_cycles"] / vc["valu_insts"], 3),
+                "source": "profiles/valu_4k_x8.json counts per launch over duration_us",
+            }
 
     configs = None
     if (args.only == "all" or args.config_only) and not args.no_configs:
@@ -302,7 +353,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = _cpu_baseline(scene, args.mode, args.cpu_seconds)
+        cpu = _cpu_baseline(args.mode, args.cpu_seconds)
 
     step_gbs = BYTES_PER_PX["fused"] * n_px / (ms_step * 1e-3) / 1e9
     res = {
@@ -312,6 +363,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
+        "clock_settle": settle,
         "ms_per_step": round(ms_step, 5),
         "higher_is_better": True,
         "scaling": "weak",
@@ -380,7 +432,7 @@ def _configs(np, torch, synth, glu, dev, stream, scene, only=None):
 def _plain_512(np, torch, synth, glu, dev, stream, out):
     I = torch.from_numpy(synth.voronoi(512, 512, n_cells=64, n_dots=20, dot_px=(2, 4), seed=1)).to(dev)
     Il = glu.downsample(I, 4, "box")
-    T = _lr_f1_torch(torch, Il).contiguous()
+    T = synth.lr_op_f1_torch(Il).contiguous()
     th = glu.empty_theta(512, 512, dev)
     o = torch.empty_like(I)
     r = {}
@@ -391,8 +443,13 @@ def _plain_512(np, torch, synth, glu, dev, stream, out):
     print("plain 512 done", file=sys.stderr, flush=True)
 
 
+JOINT_REPS = 7  # timed calls per joint form, after one untimed call; the median is reported
+
+
 def _joint_2048(np, torch, synth, glu, dev, stream, out):
-    # joint downsampling, 2048 x 2048 x8, 5 rounds (Algorithm 2)
+    # joint downsampling, 2048 x 2048 x8, 5 rounds (Algorithm 2); the calls
+    # synchronise with the host once per round, so their wall time carries
+    # host latency: one untimed call, then the median of JOINT_REPS
     I = torch.from_numpy(synth.voronoi(2048, 2048, n_cells=512, n_dots=200, dot_px=(1, 3), seed=2)).to(dev)
     L0 = glu.downsample(I, 8, "point")
     jws = None
@@ -400,22 +457,23 @@ def _joint_2048(np, torch, synth, glu, dev, stream, out):
     for mode in ("exhaustive", "fast"):
         walls = []
         stats = None
-        for rep in range(3):
+        for rep in range(JOINT_REPS + 1):
             torch.cuda.synchronize()
             t = time.perf_counter()
             Lj, thj, ej, stats, _ = glu.joint_downsample(I, L0, 8, 3, EPS, mode, max_iter=5, log_capacity=0,
                                                          workspace=jws)
             torch.cuda.synchronize()
             walls.append(time.perf_counter() - t)
+        walls = sorted(walls[1:])
         Tj = _lr_f2_torch(torch, Lj)
         oj = torch.empty_like(I)
         thj2 = glu.empty_theta(2048, 2048, dev)
         ms_sa = _events_ms(torch, stream, lambda i: glu.search_apply(I, Lj, Tj, 8, 3, EPS, mode, theta=thj2, out=oj),
                            100, 10)
         r[mode] = {
-            "wall_ms": round(1e3 * sorted(walls)[1], 3),
+            "wall_ms": round(1e3 * walls[len(walls) // 2], 3),
             "search_apply_after_us": round(1e3 * ms_sa, 2),
-            "Mpx_s": round(2048 * 2048 / sorted(walls)[1] / 1e6, 1),
+            "Mpx_s": round(2048 * 2048 / walls[len(walls) // 2] / 1e6, 1),
             "rounds_run": stats["rounds_run"],
             "n_large": stats["n_large"][: stats["rounds_run"]],
             "n_components": stats["n_components"][: stats["rounds_run"]],
@@ -426,27 +484,27 @@ def _joint_2048(np, torch, synth, glu, dev, stream, out):
     # gradient-driven form of the joint downsampling on the same image and
     # I_low0, 5 steps, eta 0.01, the best I_low kept
     walls = []
-    for rep in range(3):
+    for rep in range(JOINT_REPS + 1):
         torch.cuda.synchronize()
         t = time.perf_counter()
         Lg, thg, eg, sums, best = glu.joint_downsample_grad(I, L0, 8, 3, EPS, "exhaustive", eta=0.01, n_steps=5)
         torch.cuda.synchronize()
         walls.append(time.perf_counter() - t)
-    r["gradient_exhaustive"] = {"wall_ms": round(1e3 * sorted(walls)[1], 3), "eta": 0.01, "steps": 5,
+    walls = sorted(walls[1:])
+    r["gradient_exhaustive"] = {"wall_ms": round(1e3 * walls[len(walls) // 2], 3), "eta": 0.01, "steps": 5,
                                 "err_sums": [round(v, 3) for v in sums], "best_step": best}
     out["joint_2048_x8_5rounds"] = r
     print("joint done", file=sys.stderr, flush=True)
 
 
 def _configs_rest(np, torch, synth, glu, dev, stream, scene, out):
-    # 60 frames of 3840 x 2160, float16 storage, one persistent launch under
+    # 60 frames of 3840 x 2160, float16 storage, one batched launch under
     # a captured graph; frame t is the scene crop at column 3 t
     canvas = torch.from_numpy(scene.canvas.astype(np.float32)).to(dev)
     items = []
-    for t in range(60):
-        If = _noisy_crop(torch, canvas, 0, 3 * t, H, W, 7000 + t, torch.float16)
+    for If in synth.video_frames_torch(canvas, 60, torch.float16):
         Ilf = glu.downsample(If, S, "point")
-        items.append(dict(I=If, I_low=Ilf, T_low=_lr_f1_torch(torch, Ilf).half().contiguous(),
+        items.append(dict(I=If, I_low=Ilf, T_low=synth.lr_op_f1_torch(Ilf).half().contiguous(),
                           T_hat=torch.empty((H, W, 3), dtype=torch.float16, device=dev), s=S, k=K))
     del canvas
     r = {}
@@ -482,7 +540,7 @@ def _configs_rest(np, torch, synth, glu, dev, stream, scene, out):
     ow = torch.empty_like(I)
     sweep = {"k_at_s8": {}, "s_at_k3": {}}
     Il8 = glu.downsample(I, 8, "point")
-    T8 = _lr_f1_torch(torch, Il8).contiguous()
+    T8 = synth.lr_op_f1_torch(Il8).contiguous()
     # the host-side set-up above leaves the GPU idle: about 100 ms of the
     # k = 3 step first, so that the sweep's first shape is not timed while
     # the clocks ramp up
@@ -499,7 +557,7 @@ def _configs_rest(np, torch, synth, glu, dev, stream, scene, out):
         sweep["k_at_s8"][str(kk)] = row
     for ss in (2, 3, 4, 6, 8, 16, 32, 64, 128):
         Ils = glu.downsample(I, ss, "point")
-        Ts = _lr_f1_torch(torch, Ils).contiguous()
+        Ts = synth.lr_op_f1_torch(Ils).contiguous()
         row = {}
         for mode in ("exhaustive", "fast"):
             ms = _events_ms(torch, stream,
@@ -526,16 +584,16 @@ def _configs_rest(np, torch, synth, glu, dev, stream, scene, out):
         mse = float(((a.double() - b.double()) ** 2).mean())
         return round(10.0 * np.log10(1.0 / mse), 3) if mse > 0 else float("inf")
 
-    target = _lr_f1_torch(torch, I)
+    target = synth.lr_op_f1_torch(I)
     q = {}
     for mode in ("exhaustive", "fast", "gnu"):
         o, _ = glu.search_apply(I, Il8, T8, 8, 3, EPS, mode, store_theta=False)
         q["glu_" + mode if mode != "gnu" else "gnu"] = psnr(o, target)
     Lj, _, _, _, _ = glu.joint_downsample(I, Il8, 8, 3, EPS, "exhaustive", max_iter=5, log_capacity=0)
-    o, _ = glu.search_apply(I, Lj, _lr_f1_torch(torch, Lj).contiguous(), 8, 3, EPS, "exhaustive", store_theta=False)
+    o, _ = glu.search_apply(I, Lj, synth.lr_op_f1_torch(Lj).contiguous(), 8, 3, EPS, "exhaustive", store_theta=False)
     q["glu_exhaustive_alg2_5rounds"] = psnr(o, target)
     Lg, _, _, _, _ = glu.joint_downsample_grad(I, Il8, 8, 3, EPS, "exhaustive", eta=0.01, n_steps=5)
-    o, _ = glu.search_apply(I, Lg, _lr_f1_torch(torch, Lg).contiguous(), 8, 3, EPS, "exhaustive", store_theta=False)
+    o, _ = glu.search_apply(I, Lg, synth.lr_op_f1_torch(Lg).contiguous(), 8, 3, EPS, "exhaustive", store_theta=False)
     q["glu_exhaustive_gradient_5steps"] = psnr(o, target)
     up = torch.nn.functional.interpolate(T8.permute(2, 0, 1).unsqueeze(0), size=(H, W), mode="bilinear",
                                          align_corners=False)[0].permute(1, 2, 0)
@@ -550,8 +608,12 @@ def _configs_rest(np, torch, synth, glu, dev, stream, scene, out):
 
     # target-free overlap: the search does not depend on the LR target, so
     # for video it runs on one stream while the LR operator of the same frame
-    # runs on another, and the apply joins them.  The operator stands in for
-    # an LR network: four 3x3 convolutions (3-32-32-32-3 channels) at 480x270.
+    # runs on another, and the apply joins them (paper_2307_09582_amd.video,
+    # the schedule tests/test_gpu_overlap.py checks against the oracle).  The
+    # operator stands in for an LR network: four 3x3 convolutions
+    # (3-32-32-32-3 channels) at 480x270.
+    from paper_2307_09582_amd import video
+
     torch.manual_seed(9)
     convs = [torch.nn.Conv2d(ci, co, 3, padding=1).to(dev).half()
              for ci, co in ((3, 32), (32, 32), (32, 32), (32, 3))]
@@ -566,54 +628,30 @@ def _configs_rest(np, torch, synth, glu, dev, stream, scene, out):
 
     canvas = torch.from_numpy(scene.canvas.astype(np.float32)).to(dev)
     nf = 24
-    frames = [_noisy_crop(torch, canvas, 0, 3 * t, H, W, 9000 + t, torch.float16) for t in range(nf)]
+    frames = [synth.noisy_crop_torch(canvas, 0, 3 * t, H, W, 9000 + t, torch.float16) for t in range(nf)]
     del canvas
-    lows = [torch.empty((H // S, W // S, 3), dtype=torch.float16, device=dev) for _ in range(nf)]
-    targets = [None] * nf
-    thetas = [glu.empty_theta(H, W, dev) for _ in range(nf)]
-    outs = [torch.empty((H, W, 3), dtype=torch.float16, device=dev) for _ in range(nf)]
     side = torch.cuda.Stream()  # default priority
-
-    def down(t):
-        lows[t] = glu.downsample(frames[t], S, "point")
+    bufs = video.VideoBuffers(frames, S)
 
     def sequential():
-        for t in range(nf):
-            down(t)
-            targets[t] = lr_op(lows[t])
-            glu.search_apply(frames[t], lows[t], targets[t], S, K, EPS, "exhaustive", theta=thetas[t], out=outs[t])
+        video.sequential(frames, lr_op, S, K, EPS, "exhaustive", bufs=bufs)
 
     def overlapped():
-        main = torch.cuda.current_stream()
-        done = [torch.cuda.Event() for _ in range(nf)]
-        for t in range(nf):
-            down(t)
-            ev = torch.cuda.Event()
-            ev.record(main)
-            side.wait_event(ev)
-            with torch.cuda.stream(side):
-                targets[t] = lr_op(lows[t])
-                done[t].record(side)
-            glu.search(frames[t], lows[t], S, K, EPS, "exhaustive", theta=thetas[t])
-            if t > 0:  # the previous frame's apply, behind this frame's search
-                main.wait_event(done[t - 1])
-                glu.apply(thetas[t - 1], targets[t - 1], S, K, out=outs[t - 1])
-        main.wait_event(done[nf - 1])
-        glu.apply(thetas[nf - 1], targets[nf - 1], S, K, out=outs[nf - 1])
+        video.overlapped(frames, lr_op, side, S, K, EPS, "exhaustive", bufs=bufs)
 
     with torch.no_grad():
-        down(0)
-        ms_op = _events_ms(torch, stream, lambda i: lr_op(lows[0]), 50, 5)
+        video.sequential(frames[:1], lr_op, S, K, EPS, "exhaustive")
+        ms_op = _events_ms(torch, stream, lambda i: lr_op(bufs.lows[0]), 50, 5)
         ms_seq = _events_ms(torch, stream, lambda i: sequential(), 3, 1)
         ms_ovl = _events_ms(torch, stream, lambda i: overlapped(), 3, 1)
-        ovl_out = [o.clone() for o in outs]
+        ovl_out = [o.clone() for o in bufs.outs]
         sequential()
         torch.cuda.synchronize()
-        ref = [o.clone() for o in outs]
+        ref = [o.clone() for o in bufs.outs]
         same = all(torch.equal(a, b) for a, b in zip(ref, ovl_out))
         del ovl_out
 
-        # the same two pipelines captured as graphs (the side stream joins the
+        # the same two schedules captured as graphs (the side stream joins the
         # capture through the events), which takes host launch cost out; each
         # replay is checked against the eager result, with eager work between
         graphs, replay_ok = {}, True
@@ -628,12 +666,12 @@ def _configs_rest(np, torch, synth, glu, dev, stream, scene, out):
             with torch.cuda.graph(g):
                 fn()
             for rep in range(3):
-                for o in outs:
+                for o in bufs.outs:
                     o.zero_()
                 g.replay()
                 torch.cuda.synchronize()
-                replay_ok &= all(torch.equal(a, b) for a, b in zip(ref, outs))
-                lr_op(lows[0]).sum().item()
+                replay_ok &= all(torch.equal(a, b) for a, b in zip(ref, bufs.outs))
+                lr_op(bufs.lows[0]).sum().item()
             graphs[name] = g
         ms_gseq = _events_ms(torch, stream, lambda i: graphs["sequential"].replay(), 10, 2)
         ms_govl = _events_ms(torch, stream, lambda i: graphs["overlapped"].replay(), 10, 2)
@@ -641,26 +679,11 @@ def _configs_rest(np, torch, synth, glu, dev, stream, scene, out):
 
         # latency of one frame on an idle GPU, from its downsample to its
         # last T_hat write; the overlapped form submits the search first
-        def one_seq(t):
-            down(t)
-            targets[t] = lr_op(lows[t])
-            glu.search_apply(frames[t], lows[t], targets[t], S, K, EPS, "exhaustive", theta=thetas[t], out=outs[t])
-
-        def one_ovl(t):
-            main = torch.cuda.current_stream()
-            down(t)
-            ev, done = torch.cuda.Event(), torch.cuda.Event()
-            ev.record(main)
-            glu.search(frames[t], lows[t], S, K, EPS, "exhaustive", theta=thetas[t])
-            side.wait_event(ev)
-            with torch.cuda.stream(side):
-                targets[t] = lr_op(lows[t])
-                done.record(side)
-            main.wait_event(done)
-            glu.apply(thetas[t], targets[t], S, K, out=outs[t])
-
         lat, lat_ok = {}, True
-        for name, fn in (("sequential", one_seq), ("overlapped", one_ovl)):
+        forms = (("sequential", lambda t: video.one_frame_sequential(frames[t], lr_op, S, K, EPS, "exhaustive", bufs, t)),
+                 ("overlapped", lambda t: video.one_frame_overlapped(frames[t], lr_op, side, S, K, EPS, "exhaustive",
+                                                                     bufs, t)))
+        for name, fn in forms:
             fn(0)
             torch.cuda.synchronize()
             us = []
@@ -673,7 +696,7 @@ def _configs_rest(np, torch, synth, glu, dev, stream, scene, out):
                 us.append(1e3 * a.elapsed_time(b))
             us.sort()
             lat[name] = {"median_us": round(us[nf // 2], 1), "p90_us": round(us[(9 * nf) // 10], 1)}
-            lat_ok &= all(torch.equal(x, y) for x, y in zip(ref, outs))
+            lat_ok &= all(torch.equal(x, y) for x, y in zip(ref, bufs.outs))
     out["video_overlap_4k_f16"] = {
         "frames": nf, "lr_operator_us": round(1e3 * ms_op, 1),
         "eager": {"sequential_ms": round(ms_seq, 3), "overlapped_ms": round(ms_ovl, 3),
@@ -684,25 +707,23 @@ def _configs_rest(np, torch, synth, glu, dev, stream, scene, out):
         "latency_one_frame": lat,
         "outputs_equal": same, "graph_replays_equal": replay_ok, "latency_runs_equal": lat_ok,
     }
-    del frames, lows, targets, thetas, outs
+    del frames, bufs
     torch.cuda.synchronize()
     print("overlap done", file=sys.stderr, flush=True)
 
     # uneven batch: 64 images, sizes 720x480 .. 6000x4000, s in {4, 8, 16},
     # k in {3, 5}; crops of one seeded canvas with the same cell density
     specs = synth.uneven_batch_specs(64, seed=4)
-    big = synth.make_scene(4000, 6000, 2894, 1157, (1, 3), seed=4)
+    uc = synth.UNEVEN_CANVAS
+    big = synth.make_scene(uc["H"], uc["W"], uc["n_cells"], uc["n_dots"], uc["dot_px"], seed=uc["seed"])
     canvas = torch.from_numpy(big.canvas.astype(np.float32)).to(dev)
-    rng = np.random.default_rng(44)
+    imgs, _ = synth.uneven_batch_torch(canvas, specs, torch.float32)
     items = []
-    for i, sp in enumerate(specs):
-        y0 = int(rng.integers(0, 4000 - sp["H"] + 1))
-        x0 = int(rng.integers(0, 6000 - sp["W"] + 1))
-        Iu = _noisy_crop(torch, canvas, y0, x0, sp["H"], sp["W"], sp["seed"], torch.float32)
+    for Iu, sp in zip(imgs, specs):
         Ilu = glu.downsample(Iu, sp["s"], "point")
-        items.append(dict(I=Iu, I_low=Ilu, T_low=_lr_f1_torch(torch, Ilu).contiguous(),
+        items.append(dict(I=Iu, I_low=Ilu, T_low=synth.lr_op_f1_torch(Ilu).contiguous(),
                           T_hat=torch.empty_like(Iu), s=sp["s"], k=sp["k"]))
-    del canvas
+    del canvas, imgs
     r = {}
     npx = sum(sp["H"] * sp["W"] for sp in specs)
     for mode in ("exhaustive", "fast"):
@@ -739,9 +760,9 @@ def _configs_rest(np, torch, synth, glu, dev, stream, scene, out):
     alpha5 = torch.empty((B5, N5, N5), dtype=torch.float32, device=dev)
     T5 = torch.empty((B5, N5 // 8, N5 // 8, 3), dtype=torch.float32, device=dev)
     for b in range(B5):
-        Ib = _noisy_crop(torch, canvas, (b % 2) * 1000, (b // 2) * 370, N5, N5, 8000 + b, torch.float32)
+        Ib = synth.noisy_crop_torch(canvas, (b % 2) * 1000, (b // 2) * 370, N5, N5, 8000 + b, torch.float32)
         Ilb = glu.downsample(Ib, 8, "point")
-        T5[b] = _lr_f1_torch(torch, Ilb)
+        T5[b] = synth.lr_op_f1_torch(Ilb)
         glu.search(Ib, Ilb, 8, 3, EPS, theta=glu.Theta(code5[b], alpha5[b]))
     del canvas
     th5 = glu.Theta(code5, alpha5)
@@ -775,38 +796,118 @@ def _configs_rest(np, torch, synth, glu, dev, stream, scene, out):
     return out
 
 
-def _cpu_baseline(scene, mode, seconds):
-    """The float64 oracle, as it stands, on a band of rows of frame 0."""
+def _cpu_baseline(mode, seconds):
+    """The float64 oracle, as it stands, timed on the host cores in a child
+    process that never touches the GPU (see _cpu_child); returns its entry."""
+    import subprocess
+
+    cmd = [sys.executable, os.path.abspath(__file__), "--cpu-child", "--mode", mode, "--cpu-seconds", str(seconds)]
+    r = subprocess.run(cmd, capture_output=True, text=True, timeout=900)
+    if r.returncode != 0:
+        raise RuntimeError("oracle timing failed (%d): %s" % (r.returncode, r.stderr[-2000:]))
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
+# rows of the frame handed to one oracle worker of the pool, set before the fork
+_POOL_ARGS = {}
+
+
+def _pool_band(job):
+    import numpy as np
+
+    import oracle as O
+
+    y0, y1, mode = job
+    a = _POOL_ARGS
+    pix = np.arange(y0 * a["W"], y1 * a["W"], dtype=np.int64)
+    r = O.search(a["I"], a["L"], S, K, EPS, mode, pixels=pix)
+    out = O.apply(r.a, r.b, r.alpha, a["T"])
+    return float(out.sum())
+
+
+def _cpu_child(mode, seconds):
+    """Oracle timings on this host (no GPU use in this process): the 4K x8
+    frame's search + apply in both modes on one core and over a pool of all
+    cores (row bands), the 512^2 box x4 workload on one core, and Algorithm 2
+    on the 2048^2 x8 workload (5 rounds, one core).  Samples that cover part
+    of a workload are labelled as extrapolations.  Prints one JSON line."""
+    import multiprocessing as mp
+
     import numpy as np
 
     import oracle as O
     import synth
 
+    cores = len(os.sched_getaffinity(0))
+    workers = max(1, min(cores, 16))
+    scene = synth.scene_4k()
     I = scene.frame(0, sigma=0.01, dtype=np.float32)
     L = O.downsample_point(I, S)
     T = synth.lr_op_f1(L)
 
-    def run(rows):
+    def band(m, rows):
         pix = np.arange(rows * W, dtype=np.int64)
         t = time.perf_counter()
-        r = O.search(I, L, S, K, EPS, mode, pixels=pix)
+        r = O.search(I, L, S, K, EPS, m, pixels=pix)
         O.apply(r.a, r.b, r.alpha, T)
         return time.perf_counter() - t
 
-    probe_rows = 8
-    tp = run(probe_rows)
-    rows = int(max(8, min(H, probe_rows * seconds / max(tp, 1e-3))))
-    rows = (rows // 8) * 8 or 8
-    dt = run(rows)
-    n = rows * W
-    return {
-        "value": round(n / dt / 1e6, 4),
+    entries = {}
+    for m, share in ((mode, 0.5), ("fast" if mode == "exhaustive" else "exhaustive", 0.2)):
+        tp = band(m, 8)
+        rows = int(max(8, min(H, 8 * seconds * share / max(tp, 1e-3)))) // 8 * 8
+        dt = band(m, rows)
+        entries["m0_%s_1core" % m] = {
+            "Mpx_s": round(rows * W / dt / 1e6, 4), "cores": 1, "seconds": round(dt, 2),
+            "sample": "rows 0..%d of the 3840x2160 frame (%d px)%s" % (
+                rows - 1, rows * W, "" if rows == H else ", extrapolated to the frame"),
+        }
+    # the pool: workers forked after the inputs exist, each searching bands of rows
+    _POOL_ARGS.update(I=I, L=L, T=T, W=W)
+    nb = 4 * workers
+    edges = [round(i * H / nb) for i in range(nb + 1)]
+    ctx = mp.get_context("fork")
+    with ctx.Pool(workers) as pool:
+        pool.map(_pool_band, [(0, 1, mode)] * workers)  # workers up
+        for m in ("exhaustive", "fast"):
+            t = time.perf_counter()
+            pool.map(_pool_band, [(edges[i], edges[i + 1], m) for i in range(nb)], chunksize=1)
+            dt = time.perf_counter() - t
+            entries["m0_%s_pool" % m] = {"Mpx_s": round(H * W / dt / 1e6, 4), "cores": workers,
+                                         "seconds": round(dt, 2),
+                                         "sample": "the whole 3840x2160 frame in %d row bands" % nb}
+    # 512 x 512, box x4, one core, both modes, whole image
+    I1 = synth.voronoi(512, 512, n_cells=64, n_dots=20, dot_px=(2, 4), seed=1)
+    L1 = O.downsample_box(I1, 4)
+    T1 = synth.lr_op_f1(L1)
+    for m in ("exhaustive", "fast"):
+        t = time.perf_counter()
+        r = O.search(I1, L1, 4, K, EPS, m)
+        O.apply(r.a, r.b, r.alpha, T1)
+        dt = time.perf_counter() - t
+        entries["c1_512_box4_%s_1core" % m] = {"Mpx_s": round(512 * 512 / dt / 1e6, 4), "cores": 1,
+                                               "seconds": round(dt, 2), "sample": "whole image"}
+    # Algorithm 2, 2048 x 2048 x8, 5 rounds, one core (sequential by definition)
+    I2 = synth.voronoi(2048, 2048, n_cells=512, n_dots=200, dot_px=(1, 3), seed=2)
+    L2 = O.downsample_point(I2, 8)
+    t = time.perf_counter()
+    res = O.joint_downsample(I2, L2, 8, K, EPS, "exhaustive", O.TAU, 5)
+    dt = time.perf_counter() - t
+    entries["c2_2048_x8_alg2_5rounds_1core"] = {
+        "Mpx_s": round(2048 * 2048 / dt / 1e6, 4), "cores": 1, "seconds": round(dt, 2),
+        "sample": "whole workload: initial search, 5 rounds (%s large-error px, %s components, %s kept)" % (
+            res.n_large, res.n_components, res.n_accepted),
+    }
+    head = entries["m0_%s_1core" % mode]
+    print(json.dumps({
+        "value": head["Mpx_s"],
         "unit": "Mpixel/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": "%s search + apply of rows 0..%d of the 3840x2160 frame (%d px, %.1f s), float64 NumPy, "
-                  "one thread" % (mode, rows - 1, n, dt),
-    }
+        "sample": "%s search + apply, %s; float64 NumPy, one thread" % (mode, head["sample"]),
+        "host_cores": cores,
+        "entries": entries,
+    }), flush=True)
 
 
 if __name__ == "__main__":
