@@ -51,6 +51,7 @@ struct BwdArgs {
   int32_t nb;           // LR cells per workgroup (one LR row), nb * k^2 <= 256
   int32_t rows_chunk;   // HR rows staged per chunk
   int32_t groups_x;     // workgroups per LR row
+  int32_t ring_blocks;  // pass 2: workgroups of border cells (the rest take the interior)
   uint32_t s_magic;     // floor(2^32 / s) for udiv_rt
   uint32_t vec;         // VEC_THETA | VEC_G | VEC_T(dalpha rows)
   // element offsets between the images of a batch (blockIdx.y)
@@ -601,51 +602,138 @@ static bool reg_geometry(int s, int k, int C, int& P) {
   return 16 * reg_lds_words(reg_geom(s, P, k), k, C) <= 64 * 1024;
 }
 
+// Pass 2: dL/dT_low[q] = sum over window offsets o = (dy, dx) of S[o][c]
+// for the cells c whose offset o points at q.  The apply reads a window
+// position outside the LR image as the nearest in-image cell, so such a
+// position's gradient goes to that cell too.
+// * Border cells (the ring of cells on the first or last row or column), in
+//   the first ring_blocks workgroups: per offset every c with
+//   clamp(c + d) = q, in ascending order.  One thread per (cell, offset)
+//   sums that offset's sources (at most (r + 1)^2, loaded together), then
+//   one thread per cell adds the k^2 partial sums in offset order: every
+//   load of the ring is in flight at once, so the few ring workgroups finish
+//   within the interior's time.  Codes from the search never point outside
+//   the image, and then every extra source holds zero sums.
+// * Interior cells, one thread each, in the remaining workgroups: the source
+//   of offset o is c = q - (dy, dx) alone, in the image for every offset
+//   when k = 3.
+__device__ __forceinline__ void ring_cell(int64_t i, int h, int w, int& qy, int& qx) {
+  // row 0, row h - 1 (h > 1), then columns 0 and w - 1 (w > 1) of rows
+  // 1 .. h - 2
+  const int rows2 = h > 1 ? 2 : 1, per = w > 1 ? 2 : 1;
+  if (i < (int64_t)rows2 * w) {
+    const int j = (int)i;
+    qy = j < w ? 0 : h - 1;
+    qx = j < w ? j : j - w;
+  } else {
+    const int j = (int)(i - (int64_t)rows2 * w);
+    qy = 1 + j / per;
+    qx = (j % per) ? w - 1 : 0;
+  }
+}
+
+// source rows (or columns) lo .. hi of offset component dd at q in an axis
+// of n cells: every c with clamp(c + dd) = q, at most r + 1 of them
+__device__ __forceinline__ void clamp_sources(int q, int dd, int n, int& lo, int& hi) {
+  if (n == 1) {
+    lo = 0;
+    hi = 0;
+  } else if (q == 0 && dd <= 0) {
+    lo = 0;
+    hi = min(n - 1, -dd);
+  } else if (q == n - 1 && dd >= 0) {
+    lo = max(0, n - 1 - dd);
+    hi = n - 1;
+  } else {
+    lo = hi = q - dd;  // empty when outside [0, n)
+    if (lo < 0 || lo >= n) hi = lo - 1;
+  }
+}
+
 template <int KW, int C>
 __global__ __launch_bounds__(256) void k_bwd_lr(const BwdArgs a0) {
   const BwdArgs a = batch_image<float>(a0);  // T is not read here
-  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t hw = (int64_t)a.h * a.w;
-  if (q >= hw) return;
-  const int qy = (int)(q / a.w), qx = (int)(q - (int64_t)qy * a.w);
+  const int h = a.h, w = a.w;
+  const int64_t hw = (int64_t)h * w;
   const int k = KW > 0 ? KW : a.k;
   const int r = k / 2, K2 = k * k;
+  if ((int)blockIdx.x < a.ring_blocks) {
+    __shared__ float part[256 * C];
+    const int cpb = 256 / K2;  // ring cells per workgroup
+    const int t = (int)threadIdx.x;
+    const int cl = t / K2, o = t - cl * K2;
+    const int64_t inner = (h > 2 && w > 2) ? (int64_t)(h - 2) * (w - 2) : 0;
+    const int64_t ci = (int64_t)blockIdx.x * cpb + cl;
+    const bool live = cl < cpb && ci < hw - inner;
+    int qy = 0, qx = 0;
+    float p[C];
+#pragma unroll
+    for (int ch = 0; ch < C; ++ch) p[ch] = 0.f;
+    if (live) {
+      ring_cell(ci, h, w, qy, qx);
+      int y0, y1, x0, x1;
+      clamp_sources(qy, o / k - r, h, y0, y1);
+      clamp_sources(qx, o % k - r, w, x0, x1);
+      if constexpr (KW > 0) {
+        constexpr int NS = KW / 2 + 1;
+#pragma unroll
+        for (int iy = 0; iy < NS; ++iy)
+#pragma unroll
+          for (int ix = 0; ix < NS; ++ix) {
+            const int cy = y0 + iy, cx = x0 + ix;
+            const bool v = cy <= y1 && cx <= x1;
+            const float* src = a.S + ((int64_t)o * hw + (v ? (int64_t)cy * w + cx : 0)) * C;
+#pragma unroll
+            for (int ch = 0; ch < C; ++ch) p[ch] += v ? src[ch] : 0.0f;
+          }
+      } else {
+        for (int cy = y0; cy <= y1; ++cy)
+          for (int cx = x0; cx <= x1; ++cx) {
+            const float* src = a.S + ((int64_t)o * hw + (int64_t)cy * w + cx) * C;
+#pragma unroll
+            for (int ch = 0; ch < C; ++ch) p[ch] += src[ch];
+          }
+      }
+    }
+#pragma unroll
+    for (int ch = 0; ch < C; ++ch) part[t * C + ch] = p[ch];
+    __syncthreads();
+    if (live && o == 0) {
+      float acc[C];
+#pragma unroll
+      for (int ch = 0; ch < C; ++ch) acc[ch] = 0.f;
+      for (int oo = 0; oo < K2; ++oo)
+#pragma unroll
+        for (int ch = 0; ch < C; ++ch) acc[ch] += part[(t + oo) * C + ch];
+      float* out = a.dT + (int64_t)qy * a.dT_stride + (int64_t)qx * C;
+#pragma unroll
+      for (int ch = 0; ch < C; ++ch) out[ch] = acc[ch];
+    }
+    return;
+  }
+  const int64_t i = (int64_t)(blockIdx.x - a.ring_blocks) * 256 + threadIdx.x;
+  const int wi = w - 2;
+  if (i >= (int64_t)(h - 2) * wi) return;
+  const int64_t ry = hw < 0x7fffffff ? (int64_t)((uint32_t)i / (uint32_t)wi) : i / wi;
+  const int qy = 1 + (int)ry, qx = 1 + (int)(i - ry * wi);
   float acc[C];
 #pragma unroll
   for (int ch = 0; ch < C; ++ch) acc[ch] = 0.f;
-  // The cells c whose window offset o = (dy, dx) points at q.  A window
-  // position outside the LR image is read (by the apply) as the nearest
-  // in-image cell, so it sends its gradient there too: on a border row or
-  // column the sources are every c with clamp(c + d) = q, in ascending
-  // order; inside, only c = q - d.  Codes from the search never point
-  // outside the image, and then every extra source holds zero sums.
-  auto sources = [](int q, int dd, int n, int& lo, int& hi) {
-    if (n == 1) {
-      lo = 0;
-      hi = 0;
-    } else if (q == 0 && dd <= 0) {
-      lo = 0;
-      hi = min(n - 1, -dd);
-    } else if (q == n - 1 && dd >= 0) {
-      lo = max(0, n - 1 - dd);
-      hi = n - 1;
-    } else {
-      lo = hi = q - dd;  // empty when outside [0, n)
-      if (lo < 0 || lo >= n) hi = lo - 1;
-    }
-  };
-  constexpr int kUnroll = KW > 0 ? KW * KW : 1;
+  // every offset unrolled for k = 3, one row of offsets for k = 5 and 7
+  constexpr int kUnroll = KW == 3 ? 9 : (KW > 0 ? KW : 1);
 #pragma unroll kUnroll
   for (int o = 0; o < K2; ++o) {
-    int y0, y1, x0, x1;
-    sources(qy, o / k - r, a.h, y0, y1);
-    sources(qx, o % k - r, a.w, x0, x1);
-    for (int cy = y0; cy <= y1; ++cy)
-      for (int cx = x0; cx <= x1; ++cx) {
-        const float* src = a.S + ((int64_t)o * hw + (int64_t)cy * a.w + cx) * C;
+    const int cy = qy - (o / k - r), cx = qx - (o % k - r);
+    if constexpr (KW == 3) {
+      const float* src = a.S + ((int64_t)o * hw + (int64_t)cy * w + cx) * C;
 #pragma unroll
-        for (int ch = 0; ch < C; ++ch) acc[ch] += src[ch];
-      }
+      for (int ch = 0; ch < C; ++ch) acc[ch] += src[ch];
+    } else {
+      const bool in = cy >= 0 && cy < h && cx >= 0 && cx < w;
+      const float* src = a.S + ((int64_t)o * hw + (in ? (int64_t)cy * w + cx : 0)) * C;
+#pragma unroll
+      for (int ch = 0; ch < C; ++ch) acc[ch] += in ? src[ch] : 0.0f;
+    }
   }
   float* out = a.dT + (int64_t)qy * a.dT_stride + (int64_t)qx * C;
 #pragma unroll
@@ -812,9 +900,16 @@ static glu_status backward_batched(int32_t n, const glu_batch_strides* bs, const
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "backward pass 1 launch");
   if (grad_T_low) {
-    const int64_t cells = (int64_t)h * w;
-    BwdKernel lr = p->k == 3 ? pick_lr_c<3>(C) : pick_lr_c<0>(C);
-    hipLaunchKernelGGL(lr, dim3((unsigned)((cells + 255) / 256), (unsigned)n), dim3(256), 0, sm, a);
+    // the ring of border cells first, then the interior cells (k_bwd_lr)
+    const int64_t inner = (h > 2 && w > 2) ? (int64_t)(h - 2) * (w - 2) : 0;
+    const int64_t ring = (int64_t)h * w - inner;
+    const int64_t cells_per_ring_block = 256 / ((int64_t)p->k * p->k);
+    const int64_t blocks_ring = (ring + cells_per_ring_block - 1) / cells_per_ring_block;
+    const int64_t blocks = blocks_ring + (inner + 255) / 256;
+    if (blocks > 0x7fffffff) return fail(GLU_ERR_UNSUPPORTED, "image too large");
+    a.ring_blocks = (int32_t)blocks_ring;
+    BwdKernel lr = p->k == 3 ? pick_lr_c<3>(C) : p->k == 5 ? pick_lr_c<5>(C) : p->k == 7 ? pick_lr_c<7>(C) : pick_lr_c<0>(C);
+    hipLaunchKernelGGL(lr, dim3((unsigned)blocks, (unsigned)n), dim3(256), 0, sm, a);
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "backward pass 2 launch");
   }
