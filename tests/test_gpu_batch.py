@@ -1,4 +1,4 @@
-"""Batched persistent execution, hipGraph capture and the autotuner."""
+"""Batched execution (one launch per kernel variant), hipGraph capture and the autotuner."""
 import os
 
 import numpy as np
