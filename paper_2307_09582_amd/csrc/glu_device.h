@@ -546,6 +546,74 @@ __device__ __forceinline__ void fast_strip(const float (&ip)[P][3], const Win& w
   }
 }
 
+// Fast search of a strip of a 3 x 3 window (Algorithm 1 with Eq. 5) with
+// the window's nine colours held in registers and the strip's pixels
+// searched one after another: one pixel's nine distances are live at a time
+// instead of P x 9, so the fused kernel fits four waves per SIMD (114 VGPRs
+// against 146).  Same arithmetic in the same order as fast_strip, so the
+// outputs are bitwise the same; BORDER skips window cells outside the image.
+template <int P, bool BORDER, typename Win>
+__device__ __forceinline__ void fast_strip_rw(const float (&ip)[P][3], const Win& win, float eps, bool gnu,
+                                              float (&best)[P], int (&code)[P], float (&alpha)[P]) {
+  float Lw[9][3];
+  bool in[9];
+#pragma unroll
+  for (int j = 0; j < 9; ++j) {
+    const float4 L = win(j);
+    Lw[j][0] = L.x;
+    Lw[j][1] = L.y;
+    Lw[j][2] = L.z;
+    in[j] = !BORDER || L.w != 0.0f;
+  }
+  static_for<0, P>([&](auto qc) {
+    constexpr int q = decltype(qc)::value;
+    float sd[9];
+    float dmin = __builtin_inff();
+    int ia = 0;
+#pragma unroll
+    for (int j = 0; j < 9; ++j) {
+      const float dx = ip[q][0] - Lw[j][0], dy = ip[q][1] - Lw[j][1], dz = ip[q][2] - Lw[j][2];
+      const float D = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+      sd[j] = __builtin_amdgcn_sqrtf(D);
+      const bool lt = in[j] && D < dmin;
+      dmin = lt ? D : dmin;
+      ia = lt ? j : ia;
+    }
+    if (gnu) {
+      best[q] = dmin;
+      code[q] = ia * 9 + ia;
+      alpha[q] = 1.0f;
+    } else {
+      const float4 A = win(ia);
+      const float sae = __builtin_amdgcn_sqrtf(dmin) + eps;
+      float bq = dmin, omb = 1.0f;
+      int bsel = ia;
+#pragma unroll
+      for (int b = 0; b < 9; ++b) {
+        const float sb = sd[b];
+        const float den = sae + sb;
+        const float om = sb * __builtin_amdgcn_rcpf(den);
+        const float om1 = 1.0f - om;
+        const float tx = fmaf(-om, A.x, ip[q][0]);
+        const float ty = fmaf(-om, A.y, ip[q][1]);
+        const float tz = fmaf(-om, A.z, ip[q][2]);
+        const float rx = fmaf(-om1, Lw[b][0], tx);
+        const float ry = fmaf(-om1, Lw[b][1], ty);
+        const float rz = fmaf(-om1, Lw[b][2], tz);
+        const float e2 = fmaf(rz, rz, fmaf(ry, ry, rx * rx));
+        const bool lt = in[b] && e2 < bq;
+        bq = lt ? e2 : bq;
+        bsel = lt ? b : bsel;
+        omb = lt ? om : omb;
+      }
+      best[q] = bq;
+      code[q] = ia * 9 + bsel;
+      alpha[q] = (bsel == ia) ? 1.0f : omb;
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  });
+}
+
 // ---------------------------------------------------------------------------
 // Staged output stores of the fused search
 // ---------------------------------------------------------------------------
@@ -601,6 +669,44 @@ __device__ __forceinline__ void store_staged(float4* buf, int lane, int C, int o
         __builtin_nontemporal_store(reinterpret_cast<const f32x4*>(buf)[idx], reinterpret_cast<f32x4*>(dst));
       else
         __builtin_nontemporal_store(reinterpret_cast<const u32x2*>(buf)[idx], reinterpret_cast<u32x2*>(dst));
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Strips of 2 or 3 float32 pixels are not whole 16-byte words, so their
+// staging is per pixel: lane l writes its strip's P pixels (C floats each)
+// to pixels P*l .. P*l + P-1 of its wave's buffer, and in store round k lane
+// l stores pixel 64 k + l, so that neighbouring lanes write neighbouring
+// pixels (one contiguous run of 64 pixels per round when the wave's strips
+// are consecutive in a row).
+template <int P>
+__device__ __forceinline__ void stage_strip_px(float* buf, int lane, int C, const float (&o)[P][4]) {
+#pragma unroll
+  for (int q = 0; q < P; ++q)
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      if (c < C) buf[(lane * P + q) * C + c] = o[q][c];
+}
+
+template <int P>
+__device__ __forceinline__ void store_staged_px(const float* buf, int lane, int C, int off, float* __restrict__ out) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+  for (int k = 0; k < P; ++k) {
+    const int m = lane + 64 * k;
+    const int st = m / P;  // owner lane of the pixel
+    const int q = m - st * P;
+    const int o = __shfl(off, st, 64);
+    if (o >= 0) {
+      float* dst = out + o + q * C;
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        if (c < C) __builtin_nontemporal_store(buf[m * C + c], dst + c);
     }
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -770,6 +876,11 @@ __device__ __forceinline__ void search_tile(const ImgDesc& d, int ty, int tx, fl
   // wave for that; lanes past the tile or the image only take part in it.
   const bool staged = FUSED && P == 4 && vecT && (d.C == 3 || d.C == 1) &&
                       (int64_t)rows * d.That_stride < 0x7fffffff;  // tile offsets fit 32 bits
+  // float32 strips of 2 or 3 pixels of the fast search: staged per pixel
+  // (the exhaustive kernels keep direct stores: the staging's registers
+  // cost them a wave per SIMD, more than the stores gain)
+  constexpr bool kStagePx = FUSED && MODE == MODE_FAST && (P == 2 || P == 3) && sizeof(T) == 4;
+  const bool staged_px = kStagePx && (int64_t)rows * d.That_stride < 0x7fffffff;
   for (int t = threadIdx.x; t - lane < nstrips; t += kThreads) {
     const int ry = t / spr;
     const int rx = (t - ry * spr) * P;
@@ -803,10 +914,17 @@ __device__ __forceinline__ void search_tile(const ImgDesc& d, int ty, int tx, fl
         for (int q = 0; q < P; ++q) al[q] = exh_alpha<KW, false>(ip[q], win, tab, eps, kw, code[q]);
       }
     } else {
-      if (interior)
-        fast_strip<KW, P, false>(ip, win, eps, kw, d.gnu != 0, best, code, al);
-      else
-        fast_strip<KW, P, true>(ip, win, eps, kw, d.gnu != 0, best, code, al);
+      if constexpr (KW == 3 && P >= 2) {
+        if (interior)
+          fast_strip_rw<P, false>(ip, win, eps, d.gnu != 0, best, code, al);
+        else
+          fast_strip_rw<P, true>(ip, win, eps, d.gnu != 0, best, code, al);
+      } else {
+        if (interior)
+          fast_strip<KW, P, false>(ip, win, eps, kw, d.gnu != 0, best, code, al);
+        else
+          fast_strip<KW, P, true>(ip, win, eps, kw, d.gnu != 0, best, code, al);
+      }
     }
     float e[P];
 #pragma unroll
@@ -837,6 +955,9 @@ __device__ __forceinline__ void search_tile(const ImgDesc& d, int ty, int tx, fl
       if (staged && full) {
         stage_strip<T, P>(sStage, lane, d.C, o);
         stage_off = (int)((int64_t)ry * d.That_stride + (int64_t)rx * d.C);
+      } else if (kStagePx && staged_px && full) {
+        stage_strip_px<P>(reinterpret_cast<float*>(sStage), lane, d.C, o);
+        stage_off = (int)((int64_t)ry * d.That_stride + (int64_t)rx * d.C);
       } else {
         store_out<T, P>(static_cast<T*>(d.That) + (int64_t)y * d.That_stride, x, d.W, d.C, vecT, full, o);
       }
@@ -845,6 +966,11 @@ __device__ __forceinline__ void search_tile(const ImgDesc& d, int ty, int tx, fl
     if (staged)
       store_staged<T>(sStage, lane, d.C, stage_off,
                       static_cast<T*>(d.That) + (int64_t)qy0 * s * d.That_stride + (int64_t)qx0 * s * d.C);
+    if constexpr (kStagePx) {
+      if (staged_px)
+        store_staged_px<P>(reinterpret_cast<const float*>(sStage), lane, d.C, stage_off,
+                           static_cast<float*>(d.That) + (int64_t)qy0 * s * d.That_stride + (int64_t)qx0 * s * d.C);
+    }
   }
 }
 
