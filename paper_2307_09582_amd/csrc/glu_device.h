@@ -714,6 +714,17 @@ __device__ __forceinline__ void store_staged_px(const float* buf, int lane, int 
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Unsigned division by a runtime divisor 1 <= d < 2^16 for 0 <= n < 2^30,
+// with m = min(2^32 - 1, floor(2^32 / d)) or m = floor((2^32 - 1) / d):
+// either is floor(2^32 / d) or one less, so the estimate q = umulhi(n, m)
+// is floor(n / d) or one less (2n / 2^32 < 1), and one correction step
+// makes it exact.
+__device__ __forceinline__ int udiv_rt(int n, int d, uint32_t m) {
+  int q = (int)__umulhi((uint32_t)n, m);
+  if ((q + 1) * d <= n) ++q;
+  return q;
+}
+
 // ---------------------------------------------------------------------------
 // One tile of search (+ apply when FUSED)
 // ---------------------------------------------------------------------------
@@ -809,10 +820,14 @@ __device__ __forceinline__ void search_tile(const ImgDesc& d, int ty, int tx, fl
   // The HR pixels of a thread's next strip are loaded one strip ahead: the
   // first strip's loads are in flight while the tile is staged, later ones
   // while the current strip is searched.
+  // strip -> (row, column) and pixel -> LR cell without integer division
+  // instructions: spr <= 1024 and s <= 1024, strip and pixel indices of a
+  // tile far below 2^30
+  const uint32_t m_spr = 0xffffffffu / (uint32_t)spr, m_s = 0xffffffffu / (uint32_t)s;
   float ipn[P][3];
   auto prefetch = [&](int t) {
     if (t >= nstrips) return;
-    const int ry = t / spr;
+    const int ry = udiv_rt(t, spr, m_spr);
     const int rx = (t - ry * spr) * P;
     const int y = qy0 * s + ry, x = qx0 * s + rx;
     if (y >= d.H || x >= d.W) return;
@@ -882,7 +897,7 @@ __device__ __forceinline__ void search_tile(const ImgDesc& d, int ty, int tx, fl
   constexpr bool kStagePx = FUSED && MODE == MODE_FAST && (P == 2 || P == 3) && sizeof(T) == 4;
   const bool staged_px = kStagePx && (int64_t)rows * d.That_stride < 0x7fffffff;
   for (int t = threadIdx.x; t - lane < nstrips; t += kThreads) {
-    const int ry = t / spr;
+    const int ry = udiv_rt(t, spr, m_spr);
     const int rx = (t - ry * spr) * P;
     const int y = qy0 * s + ry, x = qx0 * s + rx;
     float ip[P][3];
@@ -895,7 +910,7 @@ __device__ __forceinline__ void search_tile(const ImgDesc& d, int ty, int tx, fl
     const bool full = interior || (x + P <= d.W);
     int stage_off = -1;  // element offset of a staged strip from the tile's first T_hat element
     if (live) {
-    const int cy = ry / s, cx = rx / s;
+    const int cy = udiv_rt(ry, s, m_s), cx = udiv_rt(rx, s, m_s);
     const LdsWin<KW> win{sL + cy * lx + cx, lx, kw};
     const PairK* tab = sTab + (cy * tqx + cx) * tstride;
     float best[P], al[P];
@@ -986,14 +1001,7 @@ __device__ __forceinline__ void search_tile(const ImgDesc& d, int ty, int tx, fl
 // its results to an LDS buffer and stores them as one contiguous run of
 // 16-byte words (non-temporal, the output is not read again here).
 //
-// Unsigned division by a runtime divisor d < 2^16 for n < 2^31: the estimate
-// q = umulhi(n, floor(2^32 / d)) is floor(n / d) or one less; one
-// correction step makes it exact.
-__device__ __forceinline__ int udiv_rt(int n, int d, uint32_t m) {
-  int q = (int)__umulhi((uint32_t)n, m);
-  if ((q + 1) * d <= n) ++q;
-  return q;
-}
+// Divisions by s use udiv_rt (defined with the search tile).
 
 template <typename T>
 __device__ __forceinline__ float4 load_cell(const T* __restrict__ p, int C) {

@@ -585,13 +585,18 @@ glu_status glu_joint_downsample(const glu_image* I, glu_image* I_low, const glu_
   hipError_t e = hipMemsetAsync(b.flag, 0, sizeof(int) * (size_t)h * w, sm);
   if (e != hipSuccess) return hip_fail(e, "joint: clear flags");
 
-  auto full_search = [&]() -> glu_status {
+  // The one full search.  After it, Theta and E stay those of a full search
+  // against the current I_low: a trial re-searches every pixel whose window
+  // holds a replaced cell (its affected set) with the same arithmetic as the
+  // search kernels (pair constants from pair_consts, the same candidate
+  // order, the same fast-search steps), and commits exactly those pixels'
+  // Theta and E when it keeps the update; a trial that rolls back restores
+  // its cells and leaves Theta and E untouched.  So no round starts with a
+  // search, and none follows the last one.
+  {
     glu_theta th = *theta;
-    glu_status s2 = glu_search(I, I_low, p, &th, b.E, stream);
-    return s2;
-  };
-
-  if ((st = full_search())) return st;
+    if ((st = glu_search(I, I_low, p, &th, b.E, stream))) return st;
+  }
   // the initial error sum: copied with the first round's data (one
   // synchronisation per round; rounds_run = 0 reads it at the end)
   hipLaunchKernelGGL(k_jd_sum_tiles, dim3((unsigned)ntiles), dim3(256), 0, sm, b.E, n, b.partial);
@@ -678,7 +683,6 @@ glu_status glu_joint_downsample(const glu_image* I, glu_image* I_low, const glu_
   // union and flatten stride over the list with a small fixed grid
   const unsigned ugrid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(64, (n + 255) / 256));
   for (int round = 1; round <= max_iter; ++round) {
-    if (round > 1 && (st = full_search())) return st;
     hipLaunchKernelGGL(k_jd_mark, dim3((unsigned)ntiles), dim3(256), 0, sm, b.E, n, tau, b.parent, b.tile_count);
     hipLaunchKernelGGL(k_jd_scan, dim3(1), dim3(256), 0, sm, b.tile_count, (int)ntiles, b.tile_off, b.total);
     hipLaunchKernelGGL(k_jd_scatter, dim3((unsigned)ntiles), dim3(256), 0, sm, b.parent, n, b.tile_off, b.list);
@@ -865,10 +869,8 @@ glu_status glu_joint_downsample(const glu_image* I, glu_image* I_low, const glu_
   if (e != hipSuccess) return hip_fail(e, "joint: decisions");
   take_initial();
   take_pending();
-  // the returned Theta / E: the search against the final I_low
+  // the returned Theta / E: those of the search against the final I_low
   {
-    glu_theta th = *theta;
-    if ((st = glu_search(I, I_low, p, &th, b.E, stream))) return st;
     if (err) {
       e = hipMemcpyAsync(err, b.E, sizeof(float) * (size_t)n, hipMemcpyDeviceToDevice, sm);
       if (e != hipSuccess) return hip_fail(e, "joint: copy err");

@@ -174,3 +174,25 @@ def test_giant_component_box_walk():
     L0 = O.downsample_point(I, 2)
     stats, log, _ = _check(glu, I, L0, 2, 3, "exhaustive", 0.0, 1)
     assert stats["n_components"][0] == 1 and len(log) == 1
+
+
+# Theta and E returned by Algorithm 2 are maintained by the trials (a kept
+# trial commits its affected set's re-search); they must be bitwise those of
+# a full search against the returned I_low.  Cases with kept trials in both
+# modes, 3 x 3 and 5 x 5 windows, and components at the image border.
+@pytest.mark.parametrize("mode,H,W,s,k", [("exhaustive", 256, 320, 8, 3), ("fast", 256, 320, 8, 3),
+                                          ("exhaustive", 203, 157, 4, 3), ("fast", 203, 157, 3, 3),
+                                          ("exhaustive", 160, 168, 8, 5), ("fast", 150, 170, 6, 5)])
+def test_returned_theta_is_a_full_search(mode, H, W, s, k):
+    glu = _glu()
+    log_case(test="joint_theta_is_full_search", mode=mode, H=H, W=W, s=s, k=k)
+    I = synth.voronoi(H, W, n_cells=max(8, H * W // 2000), n_dots=24, dot_px=(1, 3), seed=H * 7 + W)
+    L0 = O.downsample_point(I, s)
+    dI = dev(np.ascontiguousarray(I.astype(np.float32)))
+    Lg, th, err, stats, log = glu.joint_downsample(dI, dev(np.ascontiguousarray(L0.astype(np.float32))), s, k,
+                                                   1e-3, mode, O.TAU, 4)
+    assert sum(stats["n_accepted"][: stats["rounds_run"]]) >= 1, stats
+    th2, e2 = glu.search(dI, Lg, s, k, 1e-3, mode, return_err=True)
+    assert np.array_equal(host(th.code), host(th2.code))
+    assert np.array_equal(host(th.alpha), host(th2.alpha))
+    assert np.array_equal(host(err), host(e2))
