@@ -567,14 +567,16 @@ __device__ __forceinline__ void fast_strip_rw(const float (&ip)[P][3], const Win
   }
   static_for<0, P>([&](auto qc) {
     constexpr int q = decltype(qc)::value;
-    float sd[9];
+    // squared distances; their square roots are taken in the partner loop,
+    // which GNU mode skips
+    float Dj[9];
     float dmin = __builtin_inff();
     int ia = 0;
 #pragma unroll
     for (int j = 0; j < 9; ++j) {
       const float dx = ip[q][0] - Lw[j][0], dy = ip[q][1] - Lw[j][1], dz = ip[q][2] - Lw[j][2];
       const float D = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-      sd[j] = __builtin_amdgcn_sqrtf(D);
+      Dj[j] = D;
       const bool lt = in[j] && D < dmin;
       dmin = lt ? D : dmin;
       ia = lt ? j : ia;
@@ -590,7 +592,7 @@ __device__ __forceinline__ void fast_strip_rw(const float (&ip)[P][3], const Win
       int bsel = ia;
 #pragma unroll
       for (int b = 0; b < 9; ++b) {
-        const float sb = sd[b];
+        const float sb = __builtin_amdgcn_sqrtf(Dj[b]);
         const float den = sae + sb;
         const float om = sb * __builtin_amdgcn_rcpf(den);
         const float om1 = 1.0f - om;

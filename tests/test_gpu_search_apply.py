@@ -113,6 +113,13 @@ CASES = [
     (72, 88, 8, 5, 3, "exhaustive", "f32"),
     (96, 112, 16, 5, 2, "exhaustive", "f16"),
     (41, 67, 8, 5, 1, "exhaustive", "f32"),
+    # float32 fast tiles with strips of 2 or 3 pixels (per-pixel staged T_hat)
+    (37, 41, 2, 3, 4, "fast", "f32"),
+    (50, 66, 2, 3, 1, "fast", "f32"),
+    (64, 200, 2, 3, 3, "fast", "f32"),
+    (45, 63, 3, 3, 4, "fast", "f32"),
+    (33, 36, 6, 3, 1, "fast", "f32"),
+    (97, 200, 6, 3, 3, "fast", "f32"),
 ]
 
 
@@ -413,7 +420,7 @@ def test_no_degenerate_flag(H, W, s, k, C):
 
 
 @pytest.mark.parametrize("H,W,s,k,C,dt", [(200, 264, 8, 3, 3, "f32"), (37, 53, 4, 5, 1, "f32"), (29, 31, 3, 3, 3, "f16"),
-                                           (41, 39, 4, 7, 2, "f32")])
+                                           (41, 39, 4, 7, 2, "f32"), (50, 70, 2, 3, 3, "f32"), (61, 75, 6, 3, 4, "f32")])
 def test_gnu_mode(H, W, s, k, C, dt):
     """GNU (nearest window colour, weight 1) through search, apply, the fused
     pass and a batch plan."""
