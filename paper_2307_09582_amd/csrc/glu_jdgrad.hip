@@ -145,7 +145,30 @@ __global__ __launch_bounds__(256) void k_esum_final(const double* __restrict__ p
   if (threadIdx.x == 0) *out = red[0];
 }
 
+// Best-step bookkeeping on the device, so that the steps need no host
+// synchronisation: *best is the step of least error sum so far (the first
+// on ties); step t's sum is sums[t].
+__global__ void k_best_step(const double* __restrict__ sums, int t, int* __restrict__ best) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    if (t == 0 || sums[t] < sums[*best]) *best = t;
+  }
+}
+
+// Copies the h x w x 3 LR image src into dst when step t is the best so far.
+__global__ __launch_bounds__(256) void k_copy_lr_if_best(const int* __restrict__ best, int t, float* __restrict__ dst,
+                                                         int64_t dst_stride, const float* __restrict__ src,
+                                                         int64_t src_stride, int h, int w) {
+  if (*best != t) return;
+  const int64_t n = (int64_t)h * w * 3;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const int64_t row = i / ((int64_t)w * 3), col = i - row * w * 3;
+    dst[row * dst_stride + col] = src[row * src_stride + col];
+  }
+}
+
 static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+constexpr int kMaxSteps = 64;
 
 static thread_local PinnedBuf tl_sum_pin;
 
@@ -170,8 +193,8 @@ static JdgLayout jdg_layout(int H, int W, const glu_params* p) {
   off += align256((size_t)H * W * sizeof(float));
   l.part = off;
   off += align256((size_t)ceil_div(std::max(H, 1), kSumRows) * sizeof(double));
-  l.sum = off;
-  off += align256(sizeof(double));
+  l.sum = off;  // the error sums of steps 0 .. kMaxSteps, then the best step (int)
+  off += align256((kMaxSteps + 1) * sizeof(double) + sizeof(int));
   l.total = off;
   return l;
 }
@@ -202,7 +225,7 @@ glu_status glu_joint_downsample_grad(const glu_image* I, glu_image* I_low, const
   if (I_low->height != h || I_low->width != w) return fail(GLU_ERR_SHAPE, "I_low must be ceil(H/s) x ceil(W/s)");
   if ((st = check_theta(theta, H, W, true))) return st;
   if (!(eta >= 0.0f) || !std::isfinite(eta)) return fail(GLU_ERR_PARAM, "eta must be finite and >= 0");
-  if (n_steps < 0 || n_steps > 64) return fail(GLU_ERR_PARAM, "n_steps = %d outside 0..64", n_steps);
+  if (n_steps < 0 || n_steps > kMaxSteps) return fail(GLU_ERR_PARAM, "n_steps = %d outside 0..%d", n_steps, kMaxSteps);
   if (err && reinterpret_cast<uintptr_t>(err) % 4) return fail(GLU_ERR_ALIGN, "err not aligned");
   if (!err && theta->row_stride != W && (int64_t)H * W > 0)
     return fail(GLU_ERR_SHAPE, "theta must be dense (row_stride == W) when err is NULL");
@@ -234,15 +257,21 @@ glu_status glu_joint_downsample_grad(const glu_image* I, glu_image* I_low, const
   glu_image Dimg{D, h, w, 3, (int64_t)w * 3, GLU_F32};
 
   auto search = [&]() -> glu_status { return glu_search(I, I_low, p, theta, E, stream); };
-  auto esum = [&](double& out) -> glu_status {
+  int* best_dev = reinterpret_cast<int*>(dsum + kMaxSteps + 1);
+  // step t's error sum into dsum[t], then the best-step update (and, with
+  // keep_best, the copy of the LR guide when step t is the best so far)
+  auto esum = [&](int t) -> glu_status {
     hipLaunchKernelGGL(k_esum_part, dim3((unsigned)nparts), dim3(256), 0, sm, E, theta->row_stride, H, W, part);
-    hipLaunchKernelGGL(k_esum_final, dim3(1), dim3(256), 0, sm, part, nparts, dsum);
-    PinnedBuf& pb = tl_sum_pin;
-    hipError_t e = pb.reserve(sizeof(double));
-    if (e == hipSuccess) e = hipMemcpyAsync(pb.p, dsum, sizeof(double), hipMemcpyDeviceToHost, sm);
-    if (e == hipSuccess) e = hipStreamSynchronize(sm);
+    hipLaunchKernelGGL(k_esum_final, dim3(1), dim3(256), 0, sm, part, nparts, dsum + t);
+    hipLaunchKernelGGL(k_best_step, dim3(1), dim3(64), 0, sm, dsum, t, best_dev);
+    if (keep_best) {
+      const int64_t n3 = (int64_t)h * w * 3;
+      const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(1024, (n3 + 255) / 256));
+      hipLaunchKernelGGL(k_copy_lr_if_best, dim3(grid), dim3(256), 0, sm, best_dev, t, Lbest, (int64_t)w * 3, L, Ls,
+                         h, w);
+    }
+    hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "error sum");
-    out = *pb.as<double>();
     return GLU_OK;
   };
   auto copy_L = [&](float* dst, int64_t dst_stride, const float* src, int64_t src_stride) -> glu_status {
@@ -253,11 +282,7 @@ glu_status glu_joint_downsample_grad(const glu_image* I, glu_image* I_low, const
   };
 
   if ((st = search())) return st;
-  double best = 0.0;
-  if ((st = esum(best))) return st;
-  if (err_sums) err_sums[0] = best;
-  int best_t = 0;
-  if (keep_best && n_steps > 0 && (st = copy_L(Lbest, (int64_t)w * 3, L, Ls))) return st;
+  if ((st = esum(0))) return st;
   bool fused_grad = true;
   for (int t = 1; t <= n_steps; ++t) {
     // the backward forms the self-upsampling gradient itself where it can
@@ -288,20 +313,26 @@ glu_status glu_joint_downsample_grad(const glu_image* I, glu_image* I_low, const
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "snap launch");
     if ((st = search())) return st;
-    double sum = 0.0;
-    if ((st = esum(sum))) return st;
-    if (err_sums) err_sums[t] = sum;
-    if (sum < best) {
-      best = sum;
-      best_t = t;
-      if (keep_best && (st = copy_L(Lbest, (int64_t)w * 3, L, Ls))) return st;
-    }
+    if ((st = esum(t))) return st;
   }
+  // one synchronisation: the sums and the best step
+  {
+    PinnedBuf& pb = tl_sum_pin;
+    const size_t bytes = (kMaxSteps + 1) * sizeof(double) + sizeof(int);
+    hipError_t e = pb.reserve(bytes);
+    if (e == hipSuccess) e = hipMemcpyAsync(pb.p, dsum, bytes, hipMemcpyDeviceToHost, sm);
+    if (e == hipSuccess) e = hipStreamSynchronize(sm);
+    if (e != hipSuccess) return hip_fail(e, "error sums");
+  }
+  const double* sums_h = tl_sum_pin.as<double>();
+  const int best_t = keep_best ? *reinterpret_cast<const int*>(sums_h + kMaxSteps + 1) : n_steps;
+  if (err_sums)
+    for (int t = 0; t <= n_steps; ++t) err_sums[t] = sums_h[t];
   if (keep_best && best_t != n_steps) {
     if ((st = copy_L(L, Ls, Lbest, (int64_t)w * 3))) return st;
     if ((st = search())) return st;
   }
-  if (best_step) *best_step = keep_best ? best_t : n_steps;
+  if (best_step) *best_step = best_t;
   hipError_t e = hipStreamSynchronize(sm);
   if (e != hipSuccess) return hip_fail(e, "gradient joint downsampling");
   return GLU_OK;
