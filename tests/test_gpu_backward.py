@@ -248,7 +248,8 @@ def test_batched_autograd_matches_loop():
         assert torch.allclose(T1.grad, gT[b], rtol=1e-6, atol=1e-12)
 
 
-@pytest.mark.parametrize("H,W,s,k,C", [(64, 72, 8, 3, 3), (37, 41, 4, 5, 2), (20, 9, 4, 3, 1), (8, 8, 8, 3, 3)])
+@pytest.mark.parametrize("H,W,s,k,C", [(64, 72, 8, 3, 3), (37, 41, 4, 5, 2), (20, 9, 4, 3, 1), (8, 8, 8, 3, 3),
+                                       (45, 52, 4, 7, 4), (40, 36, 3, 9, 3), (70, 6, 2, 5, 1), (5, 40, 8, 3, 3)])
 def test_border_and_invalid_codes_follow_the_clamp_rule(H, W, s, k, C):
     """Codes the search never writes: window positions outside the LR image
     (at its borders) and codes above k^4 - 1.  The apply reads the nearest
