@@ -429,6 +429,9 @@ def _configs(np, torch, synth, glu, dev, stream, scene, only=None):
     return _configs_rest(np, torch, synth, glu, dev, stream, scene, out)
 
 
+PLAIN_GRAPH_STEPS = 20  # search + apply steps per captured graph in the 512 x 512 workload
+
+
 def _plain_512(np, torch, synth, glu, dev, stream, out):
     I = torch.from_numpy(synth.voronoi(512, 512, n_cells=64, n_dots=20, dot_px=(2, 4), seed=1)).to(dev)
     Il = glu.downsample(I, 4, "box")
@@ -437,8 +440,21 @@ def _plain_512(np, torch, synth, glu, dev, stream, out):
     o = torch.empty_like(I)
     r = {}
     for mode in ("exhaustive", "fast"):
-        ms = _events_ms(torch, stream, lambda i: glu.search_apply(I, Il, T, 4, 3, EPS, mode, theta=th, out=o), 200, 20)
-        r[mode] = {"us": round(1e3 * ms, 2), "Mpx_s": round(512 * 512 / (ms * 1e-3) / 1e6, 1)}
+        def step(i):
+            glu.search_apply(I, Il, T, 4, 3, EPS, mode, theta=th, out=o)
+
+        ms = _events_ms(torch, stream, step, 200, 20)
+        # the same step captured PLAIN_GRAPH_STEPS times into one hipGraph and
+        # replayed: the host's per-call cost (argument marshalling, launch)
+        # leaves the loop, as in a serving loop over small images
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            for i in range(PLAIN_GRAPH_STEPS):
+                step(i)
+        ms_g = _events_ms(torch, stream, lambda i: g.replay(), 20, 5) / PLAIN_GRAPH_STEPS
+        del g
+        r[mode] = {"us": round(1e3 * ms, 2), "Mpx_s": round(512 * 512 / (ms * 1e-3) / 1e6, 1),
+                   "graph_us": round(1e3 * ms_g, 2), "graph_Mpx_s": round(512 * 512 / (ms_g * 1e-3) / 1e6, 1)}
     out["plain_512_box4"] = r
     print("plain 512 done", file=sys.stderr, flush=True)
 

@@ -437,3 +437,32 @@ def test_gnu_mode(H, W, s, k, C, dt):
     out, _ = glu.search_apply(it["I"], it["I_low"], it["T_low"], s, k, mode="gnu")
     assert torch.equal(out, it["T_hat"])
     plan.close()
+
+
+@pytest.mark.parametrize("mode", ["exhaustive", "fast"])
+def test_fused_step_graph_replays(mode):
+    """The fused step on the 512 x 512 box x4 image, captured three times
+    into one hipGraph and replayed three times with eager work between the
+    replays: every replay writes bitwise the eager Theta and T_hat (the
+    launches hold no memset or allocation)."""
+    glu = _glu()
+    log_case(test="fused_step_graph", mode=mode)
+    I, L, T = _inputs(512, 512, 4, seed=1, n_cells=64, n_dots=20, dot_px=(2, 4), down="box")
+    dI, dL, dT = dev(I), dev(L.astype(np.float32)), dev(T.astype(np.float32))
+    th = glu.empty_theta(512, 512)
+    out = torch.empty((512, 512, 3), dtype=torch.float32, device="cuda")
+    glu.search_apply(dI, dL, dT, 4, 3, 1e-3, mode, theta=th, out=out)
+    ref = (host(out), host(th.code), host(th.alpha))
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for _ in range(3):
+            glu.search_apply(dI, dL, dT, 4, 3, 1e-3, mode, theta=th, out=out)
+    for _ in range(3):
+        out.zero_()
+        th.code.zero_()
+        th.alpha.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(host(out), ref[0])
+        assert np.array_equal(host(th.code), ref[1]) and np.array_equal(host(th.alpha), ref[2])
