@@ -1,5 +1,6 @@
 // C ABI entry points for search, apply, fused search+apply, downsampling and
 // Theta expansion, plus the shared host helpers (errors, validation, tiles).
+#include <atomic>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -88,10 +89,10 @@ static const int kVariantStripsPerThread[] = {1, 1, 1, 2, 2, 4, 2, 4};
 
 int n_tile_variants() { return (int)(sizeof(kVariantCols) / sizeof(kVariantCols[0])); }
 
-TileChoice choose_tile(int s, int k, int mode, bool fused, bool table, int variant) {
+TileChoice choose_tile(int s, int k, int mode, bool fused, bool table, int variant, int P_override) {
   if (variant < 0 || variant >= n_tile_variants()) variant = 0;
   TileChoice tc;
-  tc.P = search_strip_pixels(s, k, mode == MODE_EXH);
+  tc.P = P_override > 0 ? P_override : search_strip_pixels(s, k, mode == MODE_EXH);
   const int cols = kVariantCols[variant];
   tc.tqx = std::max(1, cols / s);
   // the fast search keeps less per-strip state: its default tile gives each
@@ -119,6 +120,22 @@ void fill_tiles(ImgDesc& d, const TileChoice& tc) {
   d.tqx = tc.tqx;
   d.tiles_x = ceil_div(d.w, tc.tqx);
   d.tiles_y = ceil_div(d.h, tc.tqy);
+}
+
+// SIMDs of the current device (4 per compute unit), looked up once per
+// device.
+static int device_simds() {
+  static std::atomic<int> cache[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 4 * 256;
+  int v = cache[dev].load(std::memory_order_relaxed);
+  if (v == 0) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
+    v = 4 * cus;
+    cache[dev].store(v, std::memory_order_relaxed);
+  }
+  return v;
 }
 
 // window classes with their own kernels: 3, 5 and 7 are compile-time sizes, others run-time
@@ -296,8 +313,28 @@ static glu_status run_search(const glu_image* I, const glu_image* I_low, const g
   d.C = C;
   d.dtype = I->dtype;
   const int mode = p->mode == GLU_SEARCH_EXHAUSTIVE ? MODE_EXH : MODE_FAST;
-  const bool table = uses_pair_table(mode, p->k, p->s);
-  const TileChoice tc = choose_tile(p->s, p->k, mode, fused, table, tuned_variant(p->mode, p->k, p->s, I->dtype));
+  bool table = uses_pair_table(mode, p->k, p->s);
+  // A small image in strips of the default width gives the chip fewer than
+  // four waves per SIMD (a 512 x 512 image in strips of 4 pixels: one), and
+  // the search's arithmetic chains then go unhidden.  Such images take
+  // narrower strips (halved down to 1 pixel) until the launch has about
+  // four waves per SIMD, and a 3 x 3 exhaustive search of them takes the
+  // pair table at any s >= 2, so that narrow strips do not rebuild the pair
+  // constants for every pixel.  The arithmetic per pixel is unchanged, so
+  // the outputs are bitwise those of the default strips.
+  int P_small = 0;
+  {
+    const int64_t lanes_for_four_waves = (int64_t)device_simds() * 4 * 64;
+    const int64_t npx = (int64_t)H * W;
+    int P = search_strip_pixels(p->s, p->k, mode == MODE_EXH);
+    if (P > 1 && npx / P < lanes_for_four_waves) {
+      while (P > 1 && npx / P < lanes_for_four_waves) P = P % 2 == 0 ? P / 2 : 1;
+      P_small = P;
+      if (mode == MODE_EXH && kernel_has_table(MODE_EXH, p->k) && p->s >= 2) table = true;
+    }
+  }
+  const TileChoice tc =
+      choose_tile(p->s, p->k, mode, fused, table, tuned_variant(p->mode, p->k, p->s, I->dtype), P_small);
   fill_tiles(d, tc);
   d.gnu = p->mode == GLU_SEARCH_GNU;
   d.no_degen = (p->flags & GLU_FLAG_NO_DEGENERATE) != 0;

@@ -88,7 +88,8 @@ inline int search_strip_pixels(int s, int k, bool exhaustive) {
 // Default tile: about 64 HR columns by enough rows for 256 strips, shrunk
 // until the LDS of the tile fits.  `variant` selects alternatives for the
 // autotuner (0 = default).
-TileChoice choose_tile(int s, int k, int mode, bool fused, bool table, int variant);
+// P_override > 0 replaces the default strip width (it must divide s).
+TileChoice choose_tile(int s, int k, int mode, bool fused, bool table, int variant, int P_override = 0);
 int n_tile_variants();
 
 // Fills the image descriptor fields common to search / apply launches.
