@@ -32,16 +32,26 @@ class Theta:
         return tuple(self.code.shape)
 
 
+# torch's raw current-stream query (no Stream object per call); the public
+# form is the fallback
+_RAW_STREAM = getattr(torch._C, "_cuda_getCurrentRawStream", None)
+_GET_DEVICE = getattr(torch._C, "_cuda_getDevice", None)
+
+
 def _stream():
+    if _RAW_STREAM is not None and _GET_DEVICE is not None:
+        return C.c_void_p(_RAW_STREAM(_GET_DEVICE()))
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
+_DTYPES = {torch.float32: L.GLU_F32, torch.float16: L.GLU_F16}
+
+
 def _dtype_code(t: torch.Tensor) -> int:
-    if t.dtype == torch.float32:
-        return L.GLU_F32
-    if t.dtype == torch.float16:
-        return L.GLU_F16
-    raise TypeError("images must be float32 or float16, got %s" % t.dtype)
+    code = _DTYPES.get(t.dtype)
+    if code is None:
+        raise TypeError("images must be float32 or float16, got %s" % t.dtype)
+    return code
 
 
 def _img(t: torch.Tensor, name: str) -> L.glu_image:
@@ -50,10 +60,11 @@ def _img(t: torch.Tensor, name: str) -> L.glu_image:
     if not t.is_cuda:
         raise ValueError("%s must be a GPU tensor" % name)
     H, W, Cn = t.shape
-    if H * W > 0 and not (t.stride(2) == 1 and (W <= 1 or t.stride(1) == Cn)):
+    st = t.stride()
+    if H * W > 0 and not (st[2] == 1 and (W <= 1 or st[1] == Cn)):
         raise ValueError("%s rows must be dense (channels innermost, pixels adjacent)" % name)
-    stride = t.stride(0) if H > 1 else W * Cn
-    return L.glu_image(t.data_ptr() if t.numel() else None, H, W, Cn, max(stride, W * Cn), _dtype_code(t))
+    stride = st[0] if H > 1 else W * Cn
+    return L.glu_image(t.data_ptr() if H * W * Cn else None, H, W, Cn, max(stride, W * Cn), _dtype_code(t))
 
 
 def _theta(th: Theta) -> L.glu_theta:
@@ -62,13 +73,13 @@ def _theta(th: Theta) -> L.glu_theta:
         raise TypeError("theta must be (int16 code, float32 alpha)")
     if code.shape != alpha.shape or code.dim() != 2:
         raise ValueError("theta code and alpha must both be (H, W)")
-    if code.stride() != alpha.stride() or (code.numel() and code.stride(1) != 1):
-        raise ValueError("theta code and alpha must share a row-major layout")
     H, W = code.shape
-    stride = code.stride(0) if H > 1 else W
-    return L.glu_theta(
-        code.data_ptr() if code.numel() else None, alpha.data_ptr() if alpha.numel() else None, H, W, max(stride, W)
-    )
+    st = code.stride()
+    if st != alpha.stride() or (H * W and st[1] != 1):
+        raise ValueError("theta code and alpha must share a row-major layout")
+    stride = st[0] if H > 1 else W
+    n = H * W
+    return L.glu_theta(code.data_ptr() if n else None, alpha.data_ptr() if n else None, H, W, max(stride, W))
 
 
 def _per_pixel(buf, th_desc, H: int, W: int, device, name: str):
@@ -90,11 +101,22 @@ def _per_pixel(buf, th_desc, H: int, W: int, device, name: str):
     return buf
 
 
+_PARAMS: dict = {}
+
+
 def _params(s: int, k: int, eps: float, mode: str = "exhaustive", degenerate: bool = True) -> L.glu_params:
-    if mode not in _MODES:
-        raise ValueError("mode must be 'exhaustive', 'fast' or 'gnu'")
-    flags = 0 if degenerate else L.GLU_FLAG_NO_DEGENERATE
-    return L.glu_params(int(s), int(k), float(eps), _MODES[mode], flags)
+    """The glu_params of one call.  The struct is read only during the call,
+    so one instance per distinct argument set is kept and passed again."""
+    key = (s, k, eps, mode, degenerate)
+    p = _PARAMS.get(key)
+    if p is None:
+        if mode not in _MODES:
+            raise ValueError("mode must be 'exhaustive', 'fast' or 'gnu'")
+        flags = 0 if degenerate else L.GLU_FLAG_NO_DEGENERATE
+        p = L.glu_params(int(s), int(k), float(eps), _MODES[mode], flags)
+        if len(_PARAMS) < 256:
+            _PARAMS[key] = p
+    return p
 
 
 def lr_shape(H: int, W: int, s: int):
