@@ -425,6 +425,55 @@ __device__ __forceinline__ void exh_interior3(const float (&ip)[P][3], const Win
   });
 }
 
+// exh_interior3 without the table: the window's nine colours are read into
+// registers once per strip and each pair's constants are built from them
+// with pair_consts, as the table is; same pairs, same order, so the results
+// are bitwise those of exh_strip.  The scheduling barrier per pair keeps
+// one pair's constants live at a time.
+template <int P, typename Win>
+__device__ __forceinline__ void exh_interior3_rw(const float (&ip)[P][3], const Win& win, float eps, bool no_degen,
+                                                 float (&best)[P], int (&code)[P]) {
+  constexpr int K2 = 9;
+  constexpr int NP = 36;
+  float4 Lw[K2];
+#pragma unroll
+  for (int o = 0; o < K2; ++o) {
+    const float4 L = win(o);
+    Lw[o] = make_float4(L.x, L.y, L.z, 0.0f);
+  }
+#pragma unroll
+  for (int q = 0; q < P; ++q) {
+    const float dx = ip[q][0] - Lw[0].x, dy = ip[q][1] - Lw[0].y, dz = ip[q][2] - Lw[0].z;
+    best[q] = no_degen ? __builtin_inff() : fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+    code[q] = 0;
+  }
+  float d[P][3];
+  static_for<0, NP>([&](auto pc) {
+    constexpr int p = decltype(pc)::value;
+    constexpr int j = colex_j(p), i = colex_i(p);
+    if constexpr (i == 0) {
+#pragma unroll
+      for (int q = 0; q < P; ++q) {
+        d[q][0] = ip[q][0] - Lw[j].x;
+        d[q][1] = ip[q][1] - Lw[j].y;
+        d[q][2] = ip[q][2] - Lw[j].z;
+      }
+    }
+    const PairK t = pair_consts(Lw[i], Lw[j], eps);
+    constexpr int cc = i * K2 + j;
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+      const float al = pair_alpha(d[q][0], d[q][1], d[q][2], t);
+      const float e2 = pair_err2(d[q][0], d[q][1], d[q][2], al, t);
+      const bool lt = e2 < best[q];
+      best[q] = lt ? e2 : best[q];
+      code[q] = lt ? cc : code[q];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  });
+  if (no_degen) exh_lone_cell<P>(ip, win, K2, best, code);
+}
+
 // Weight of the winning exhaustive pair, recomputed with the same arithmetic
 // the loop used.
 template <int KW, bool TABLE, typename Win>
@@ -921,6 +970,8 @@ __device__ __forceinline__ void search_tile(const ImgDesc& d, int ty, int tx, fl
       if (interior) {
         if constexpr (KW == 3 && TABLE)
           exh_interior3<P>(ip, win, tab, d.no_degen != 0, best, code);
+        else if constexpr (KW == 3 && P >= 2)
+          exh_interior3_rw<P>(ip, win, eps, d.no_degen != 0, best, code);
         else
           exh_strip<KW, P, false, TABLE>(ip, win, tab, eps, kw, d.no_degen != 0, best, code);
 #pragma unroll
