@@ -311,6 +311,33 @@ def test_full_4k_x8_every_pixel_bench_launch(mode, oracle_pool):
     print(mode, dict(rep), flush=True)
 
 
+@pytest.mark.parametrize("s,mode", [(2, "exhaustive"), (3, "exhaustive"), (4, "exhaustive"), (2, "fast"),
+                                    (3, "fast"), (4, "fast")])
+def test_large_image_small_ratio_every_pixel(s, mode, oracle_pool):
+    """A 1152 x 1280 scene with the cell and dot density of the 4K scene, at
+    s = 2, 3, 4: large enough that a single-image launch keeps its default
+    strips (2, 3 and 4 pixels), so the exhaustive search runs without the
+    pair table, its window in registers.
+    Every pixel of Theta, E (a separate search) and the fused T_hat against
+    the oracle, which runs in a pool of host processes."""
+    glu = _glu()
+    log_case(test="large_image_small_ratio", s=s, mode=mode)
+    H, W = 1152, 1280
+    I = synth.make_scene(H, W, 180, 70, (1, 3), seed=5).frame(0, sigma=0.01, dtype=np.float32)
+    L = O.downsample_point(I, s)
+    T = synth.lr_op_f1(L).astype(np.float32)
+    dI, dL = dev(I), dev(L)
+    th = glu.empty_theta(H, W)
+    out = torch.empty((H, W, 3), dtype=torch.float32, device="cuda")
+    glu.search_apply(dI, dL, dev(T), s, 3, 1e-3, mode, theta=th, out=out)
+    th2, err = glu.search(dI, dL, s, 3, 1e-3, mode, return_err=True)
+    code, alpha = host(th.code), host(th.alpha)
+    assert np.array_equal(code, host(th2.code)) and np.array_equal(alpha, host(th2.alpha))
+    ref = oracle_pool.search(I, L, s, 3, 1e-3, mode)
+    rep = check_search(I, L, s, 3, 1e-3, mode, code, alpha, err=host(err), T_low=T, T_hat=host(out), ref=ref)
+    print(s, mode, dict(rep), flush=True)
+
+
 def _random_theta(H, W, s, k, rng):
     """Codes of random pairs inside each pixel's border-truncated window and
     random weights in [0, 1]; returns (code, alpha, a, b) with absolute LR
