@@ -194,6 +194,19 @@ __device__ __forceinline__ PairK pair_consts(float4 Li, float4 Lj, float eps) {
   return k;
 }
 
+// One record of the exhaustive search's pair table: e (x, y, z) and inv in
+// one 16-byte LDS word.  The scaled direction e * inv is formed when the
+// record is read, with the same products pair_consts forms, so a record
+// gives bitwise the constants pair_consts returns.
+__device__ __forceinline__ float4 pair_rec(const PairK& k) { return make_float4(k.e.x, k.e.y, k.e.z, k.ei.w); }
+
+__device__ __forceinline__ PairK pair_from_rec(float4 r) {
+  PairK k;
+  k.e = make_float4(r.x, r.y, r.z, 0.0f);
+  k.ei = make_float4(r.x * r.w, r.y * r.w, r.z * r.w, r.w);
+  return k;
+}
+
 // Eq. 4 weight on i for the pixel offset d = I_p - L_j, clamped to [0, 1]
 // (the clamp folds into the last multiply-add).
 __device__ __forceinline__ float pair_alpha(float dx, float dy, float dz, const PairK& t) {
@@ -293,7 +306,7 @@ __device__ __forceinline__ void exh_lone_cell(const float (&ip)[P][3], const Win
 
 template <int KW, int P, bool BORDER, bool TABLE, typename Win>
 __device__ __forceinline__ void exh_strip(const float (&ip)[P][3], const Win& win,
-                                          const PairK* __restrict__ tab, float eps, int kw_rt, bool no_degen,
+                                          const float4* __restrict__ tab, float eps, int kw_rt, bool no_degen,
                                           float (&best)[P], int (&code)[P]) {
   constexpr int kUnrollJ = KW == 3 ? 9 : 1;
   constexpr int kUnrollI = KW == 3 ? 8 : 2;
@@ -327,7 +340,7 @@ __device__ __forceinline__ void exh_strip(const float (&ip)[P][3], const Win& wi
     for (int i = 0; i < j; ++i) {
       PairK t;
       if (TABLE) {
-        t = tab[pair_index(i, j)];
+        t = pair_from_rec(tab[pair_index(i, j)]);
       } else {
         const float4 Li = win(i);
         if (BORDER && Li.w == 0.0f) continue;
@@ -380,7 +393,7 @@ constexpr int colex_i(int p) { return p - colex_j(p) * (colex_j(p) - 1) / 2; }
 // pair keeps only two records live (instead of all 36).
 template <int P, typename Win>
 __device__ __forceinline__ void exh_interior3(const float (&ip)[P][3], const Win& win,
-                                              const PairK* __restrict__ tab, bool no_degen, float (&best)[P],
+                                              const float4* __restrict__ tab, bool no_degen, float (&best)[P],
                                               int (&code)[P]) {
   constexpr int K2 = 9;
   constexpr int NP = 36;
@@ -395,12 +408,12 @@ __device__ __forceinline__ void exh_interior3(const float (&ip)[P][3], const Win
     }
   }
   float d[P][3];
-  PairK nxt = tab[0];
+  float4 nxt = tab[0];
   float4 Ln = win(1);
   static_for<0, NP>([&](auto pc) {
     constexpr int p = decltype(pc)::value;
     constexpr int j = colex_j(p), i = colex_i(p);
-    const PairK t = nxt;
+    const PairK t = pair_from_rec(nxt);
     if constexpr (p + 1 < NP) nxt = tab[p + 1];
     if constexpr (i == 0) {
       const float4 Lj = Ln;
@@ -478,7 +491,7 @@ __device__ __forceinline__ void exh_interior3_rw(const float (&ip)[P][3], const 
 // the loop used.
 template <int KW, bool TABLE, typename Win>
 __device__ __forceinline__ float exh_alpha(const float (&ip)[3], const Win& win,
-                                           const PairK* __restrict__ tab, float eps, int kw_rt, int code) {
+                                           const float4* __restrict__ tab, float eps, int kw_rt, int code) {
   const int kw = KW > 0 ? KW : kw_rt;
   const int K2 = kw * kw;
   const int oi = code / K2, oj = code - oi * K2;
@@ -487,7 +500,7 @@ __device__ __forceinline__ float exh_alpha(const float (&ip)[3], const Win& win,
   if (TABLE) {
     // (oi, oi) maps to a valid table slot (the record after the last pair
     // of column oi); its value is not used
-    t = tab[pair_index(oi, oj)];
+    t = pair_from_rec(tab[pair_index(oi, oj)]);
   } else {
     const float4 Li = win(oi);
     t = pair_consts(Li, Lj, eps);
@@ -782,7 +795,7 @@ __device__ __forceinline__ int udiv_rt(int n, int d, uint32_t m) {
 enum { MODE_EXH = 0, MODE_FAST = 1 };
 
 // The exhaustive search reads per-cell pair constants from an LDS table for
-// 3 x 3 windows (36 pairs, 1184 bytes per LR cell), shared by the s^2 pixels
+// 3 x 3 windows (36 pairs, 592 bytes per LR cell), shared by the s^2 pixels
 // of the cell.  Larger windows (300 pairs for 5 x 5) would shrink the tiles
 // below one strip per thread, so they build the constants of each pair once
 // per strip instead; so do 3 x 3 windows with s < 5, whose cells are too
@@ -807,7 +820,7 @@ __host__ __device__ inline int search_tile_words(int tqy, int tqx, int k, int mo
   const int r = k / 2;
   const int ncell = (tqy + 2 * r) * (tqx + 2 * r);
   int words = ncell * (fused ? 2 : 1);
-  if (mode == MODE_EXH && table) words += 2 * tqy * tqx * (n_pairs(k * k) + 1);
+  if (mode == MODE_EXH && table) words += tqy * tqx * (n_pairs(k * k) + 1);
   if (fused) words += kStageWords;
   if (fused && k <= kMaxOffTableK) words += (k * k * k * k + 3) / 4;
   return words;
@@ -849,11 +862,11 @@ __device__ __forceinline__ void search_tile(const ImgDesc& d, int ty, int tx, fl
   const int ncell = ly * lx;
   float4* sL = smem;
   float4* sT = FUSED ? smem + ncell : nullptr;
-  PairK* sTab = reinterpret_cast<PairK*>(smem + (FUSED ? 2 : 1) * ncell);
+  float4* sTab = smem + (FUSED ? 2 : 1) * ncell;
   const int tstride = n_pairs(K2) + 1;
   const int lane = (int)threadIdx.x & 63;
   // per-wave output staging (fused): after the pair table
-  float4* sStageAll = smem + (FUSED ? 2 : 1) * ncell + ((MODE == MODE_EXH && TABLE) ? 2 * tqy * tqx * tstride : 0);
+  float4* sStageAll = smem + (FUSED ? 2 : 1) * ncell + ((MODE == MODE_EXH && TABLE) ? tqy * tqx * tstride : 0);
   float4* sStage = sStageAll + ((int)threadIdx.x >> 6) * 64 * 3;
   // code -> (offset of cell a) | (offset of cell b) << 16, relative to the
   // pixel's centre at window offset 0 (fused, k <= kMaxOffTableK)
@@ -929,7 +942,7 @@ __device__ __forceinline__ void search_tile(const ImgDesc& d, int ty, int tx, fl
         const int cy = (int)(((float)c + 0.5f) * inv_tqx), cx = c - cy * tqx;
         const float4 Li = sL[cy * lx + cx + offi];
         const float4 Lj = sL[cy * lx + cx + offj];
-        sTab[c * tstride + pr] = pair_consts(Li, Lj, eps);
+        sTab[c * tstride + pr] = pair_rec(pair_consts(Li, Lj, eps));
       }
     }
     __syncthreads();
@@ -963,7 +976,7 @@ __device__ __forceinline__ void search_tile(const ImgDesc& d, int ty, int tx, fl
     if (live) {
     const int cy = udiv_rt(ry, s, m_s), cx = udiv_rt(rx, s, m_s);
     const LdsWin<KW> win{sL + cy * lx + cx, lx, kw};
-    const PairK* tab = sTab + (cy * tqx + cx) * tstride;
+    const float4* tab = sTab + (cy * tqx + cx) * tstride;
     float best[P], al[P];
     int code[P];
     if (MODE == MODE_EXH) {
